@@ -1,0 +1,175 @@
+/*
+ * khcore.h -- C ABI of the MI355X (gfx950) library for distance-generalized
+ * (k,h)-core decomposition, exact and sampled.
+ *
+ * Method: N. Tatti, "Fast computation of distance-generalized cores using
+ * sampling" (arXiv 2112.06154).  Section numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns kh_status: KH_OK (0) or a negative error code, and
+ *     never throws or aborts across the ABI.  kh_status_str() names a code.
+ *   - Graphs are simple and undirected, given as int32 CSR: row_ptr[n+1] with
+ *     row_ptr[0] = 0 and row_ptr[n] = nnz = 2m, col[nnz] holding both arc
+ *     directions, each adjacency sorted ascending, no self-loops, no
+ *     duplicates.  Vertex ids are 0..n-1.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls that take
+ *     one enqueue their GPU work on it; calls that return results in host
+ *     memory synchronise that stream before returning.
+ *   - Pointers documented as "device" must be device memory of the context's
+ *     GPU (e.g. torch tensor storage); "host" pointers are ordinary memory.
+ *   - All device arithmetic is integer.  The only floating point is the
+ *     buffer size M (computed once on the host in binary64) and the reported
+ *     density.
+ *   - A context is used by one host thread at a time.
+ */
+#ifndef KHCORE_H
+#define KHCORE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kh_status;
+#define KH_OK          0
+#define KH_EINVAL     (-1) /* bad argument (h < 1, delta outside (0,1), NULL pointer, ...) */
+#define KH_ENOMEM     (-2) /* device memory or the context's HBM budget exhausted */
+#define KH_EDEVICE    (-3) /* no usable GPU, or a HIP runtime error */
+#define KH_EGRAPH     (-4) /* CSR not canonical: asymmetric, self-loop, duplicate, unsorted, out of range */
+#define KH_EOVERFLOW  (-5) /* a core number or estimate does not fit int32 */
+#define KH_EBUSY      (-6) /* a served request is still running */
+#define KH_ENOTFOUND  (-7) /* unknown ticket */
+#define KH_ENOTIMPL   (-8) /* parameters outside what this build supports (see the entry point) */
+
+/* kh_graph_load_csr flags */
+#define KH_PTRS_HOST           0u /* row_ptr/col are host memory; the library copies them */
+#define KH_PTRS_DEVICE_BORROW  1u /* row_ptr/col are device memory the library borrows (no copy);
+                                     they must outlive the kh_graph */
+#define KH_CANONICALIZE        2u /* host pointers only: drop self-loops and duplicates,
+                                     symmetrise and sort instead of rejecting */
+#define KH_TRUST_CSR           4u /* skip validation (the caller guarantees canonical CSR) */
+
+/* kh_params.flags */
+#define KH_WANT_DENSE   1u /* also compute the densest-core estimate (Sec. 6) */
+#define KH_DENSE_PRUNE  2u /* densest core: only levels K with K(1+eps) >= (1-eps) max core */
+#define KH_EARLY_STOP   4u /* sampled path: stop once c + 1 >= |remaining| (Sec. 5 heuristic);
+                              changes the output relative to Alg. 4, off by default */
+#define KH_OUT_DEVICE   8u /* core_out / deg_out are device pointers */
+
+typedef struct kh_context kh_context;
+typedef struct kh_graph kh_graph;
+
+typedef struct kh_params {
+    int32_t  h;            /* distance bound, >= 1 (Sec. 2) */
+    double   epsilon;      /* <= 0: ExactCore.  > 0: Core (Alg. 4) with M from Eq. (buffer);
+                              the (1 +- eps) guarantee of Prop. yield needs eps <= 1/2 */
+    double   delta;        /* failure probability, in (0,1); the paper uses 0.05 (Sec. 8) */
+    uint64_t seed;         /* seed of the rank stream (ranks are geometric(1/2), Sec. 3) */
+    int32_t  M_override;   /* > 0: use this integer M instead of Eq. (buffer) for Core */
+    int32_t  M_dense_override; /* > 0: same for the densest-core pass (Alg. 7) */
+    uint32_t flags;        /* KH_WANT_DENSE | KH_DENSE_PRUNE | KH_EARLY_STOP | KH_OUT_DEVICE */
+} kh_params;
+
+typedef struct kh_result {
+    int32_t M_used;          /* integer M of the core pass (0 for ExactCore) */
+    int32_t M_dense_used;    /* integer M of the densest-core pass (0 if exact or not run) */
+    int32_t rounds;          /* bulk peeling rounds */
+    int32_t max_core;        /* largest core number */
+    int64_t dense_k;         /* densest core level K* (-1 if not computed) */
+    int64_t dense_size;      /* |F_K*|, F_K = {v : core[v] >= K} */
+    int64_t dense_R;         /* sum over F_K* of deg_h (exact) or of the estimate (sampled) */
+    double  dense_density;   /* dense_R / (2 dense_size): the (estimated) h-density |E_h|/|F| */
+    int64_t edges_traversed; /* exact path: sum over processed sources s of the alive degrees of
+                                vertices within distance h-1 of s (arcs a per-source BFS inspects) */
+    int64_t arcs_scanned;    /* physical adjacency entries read by the h-degree kernels */
+    int64_t list_elements;   /* sampled path: sample-list entries read by the union kernels */
+    double  seconds;         /* wall time of the call */
+} kh_result;
+
+/* ---- host-only helpers (no GPU needed) ----------------------------------- */
+
+const char *kh_status_str(kh_status s);
+
+/* Integer buffer size floor(M) of Eq. (buffer) (Sec. 3):
+ *   C = log(2n/delta)   (dense == 0, Alg. 4), or log(n^2/delta) (dense != 0, Alg. 7),
+ *   M = 1 + 4(2+eps)/eps^2 (C + log 8).
+ * Returns -1 for n < 1, eps <= 0 or delta outside (0,1). */
+int64_t kh_buffer_size(int64_t n, double epsilon, double delta, int32_t dense);
+
+/* Validate a host CSR against the conventions above (Sec. 2: simple undirected
+ * graph).  KH_OK, or KH_EGRAPH / KH_EINVAL. */
+kh_status kh_validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col);
+
+/* ---- context and graphs ---------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the library may hold for this context (0 = no cap beyond the GPU's).
+ * KH_EDEVICE when the device is missing. */
+kh_status kh_context_create(int32_t device, uint64_t hbm_budget_bytes, kh_context **out);
+void kh_context_destroy(kh_context *ctx);
+
+/* Make a graph resident on the context's GPU (the graph G of Sec. 2).  With
+ * KH_PTRS_HOST the CSR is validated (or canonicalised with KH_CANONICALIZE)
+ * and copied; with KH_PTRS_DEVICE_BORROW the device arrays are validated on
+ * the GPU (unless KH_TRUST_CSR) and borrowed.  n = 0 is allowed. */
+kh_status kh_graph_load_csr(kh_context *ctx, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col, uint32_t flags, void *stream, kh_graph **out);
+void kh_graph_free(kh_graph *g);
+int32_t kh_graph_n(const kh_graph *g);
+int64_t kh_graph_nnz(const kh_graph *g);
+
+/* ---- the hot path ---------------------------------------------------------- */
+
+/* Core decomposition (Sec. 2 ExactCore when epsilon <= 0, else Alg. 4 Core)
+ * of the whole graph.  core_out[n] (int32, host unless KH_OUT_DEVICE)
+ * receives c(v) or c'(v).  The result does not depend on tie-breaking, so it
+ * is unique and bit-reproducible.  With KH_WANT_DENSE, res receives the
+ * densest core level (Sec. 6; for epsilon > 0 its sum uses fresh ranks from
+ * stream 1 and M from C = log(n^2/delta), Alg. 7).  res may be NULL.
+ * Errors: KH_EINVAL (h < 1, delta outside (0,1), NULL core_out with n > 0),
+ * KH_ENOTIMPL (sampled path with n >= 2^24 or integer M > 7935),
+ * KH_EOVERFLOW (core number above INT32_MAX), KH_ENOMEM, KH_EDEVICE. */
+kh_status kh_core(kh_graph *g, const kh_params *params, int32_t *core_out, kh_result *res, void *stream);
+
+/* h-degrees deg_h(v;X) = |N(v;h,X)| - 1 (Sec. 2) of every vertex of X, where
+ * X is given by alive[n] (uint8, nonzero = in X; device; NULL = all of V).
+ * deg_out[n] (int32; host unless KH_OUT_DEVICE) gets -1 for v outside X.
+ * edges_traversed (nullable host) receives the edges-traversed count. */
+kh_status kh_hdeg(kh_graph *g, int32_t h, const uint8_t *alive, uint32_t flags, int32_t *deg_out,
+                  int64_t *edges_traversed, void *stream);
+
+/* Ranks r[v] (Sec. 3, geometric(1/2), capped at 255) of vertices 0..n-1 for
+ * (seed, stream_id): word j of vertex v is
+ *   sm(sm(sm(seed) ^ v) ^ (stream_id * 2^32 + j)), sm = SplitMix64's mixer,
+ * and r[v] counts the zero bits before the first one bit, words in order.
+ * r_out[n] is device memory. */
+kh_status kh_ranks(kh_context *ctx, int32_t n, uint64_t seed, uint32_t stream_id, uint8_t *r_out,
+                   void *stream);
+
+/* Sampled lists after initialisation (Sec. 3, B[v,i] and k[v,i] for
+ * i = 1..h on X = alive (device, NULL = V), built by the union kernels of
+ * Alg. 4's first loop), exported for inspection.  For level `level`
+ * (1 <= level <= params->h): k_out[n] (int32, -1 outside X), size_out[n]
+ * (int32), and, when members_out is not NULL, the members of each B[v,level]
+ * concatenated in vertex order, each vertex's members in ascending id order
+ * (members_cap entries available; KH_EINVAL if too small).  est_out (nullable,
+ * int64[n]) receives Alg. 1's estimate from level h.  All outputs are host
+ * memory.  Uses params->seed (stream 0) and M as kh_core does. */
+kh_status kh_sampled_lists(kh_graph *g, const kh_params *params, const uint8_t *alive, int32_t level,
+                           int32_t *k_out, int32_t *size_out, int32_t *members_out, int64_t members_cap,
+                           int64_t *est_out, void *stream);
+
+/* Densest core level of a given core map (Sec. 6): for every distinct value K
+ * of core_in[n] (host int32) let F_K = {v : core_in[v] >= K} and
+ * R_K = sum_{v in F_K} f(v; F_K), f = deg_h (epsilon <= 0) or Alg. 1's
+ * estimate with ranks of stream 1 and M from C = log(n^2/delta) (Alg. 7).
+ * Picks the K maximising R_K/|F_K| (ties: larger K) and fills res->dense_*.
+ * KH_DENSE_PRUNE restricts K as in kh_params. */
+kh_status kh_dense(kh_graph *g, const kh_params *params, const int32_t *core_in, kh_result *res, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KHCORE_H */

@@ -1,0 +1,9 @@
+"""MI355X (gfx950) distance-generalized (k,h)-core decomposition.
+
+Exact (ExactCore) and sampled (Core, Alg. 4) (k,h)-cores and the densest core
+level of Tatti, "Fast computation of distance-generalized cores using
+sampling" (arXiv 2112.06154), computed by hand-written HIP kernels behind the
+C ABI in include/khcore.h.  This package is only the Python binding.
+"""
+from .khcore import (Context, Graph, KhError, buffer_size, core, dense, hdeg, ranks, sampled_lists,  # noqa: F401
+                     status_str, validate_csr)

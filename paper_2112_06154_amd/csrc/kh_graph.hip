@@ -1,0 +1,455 @@
+// Graph residency, ranks and the bulk-peeling bookkeeping kernels (gfx950, wave64).
+//
+// Peeling follows the paper's deletion loop (ExactCore, Sec. 2; Core, Alg. 4):
+// the running maximum c of the minimum key is the core number.  Deleting every
+// vertex whose key is <= c in one round gives the same numbers as deleting one
+// minimum at a time, because the key of a vertex only depends on the vertex and
+// the remaining set and never grows when vertices are removed (for the exact
+// degree by inclusion of neighbourhoods, for the estimate by Prop. monotone).
+#include <climits>
+
+#include "kh_common.hpp"
+#include "kh_internal.hpp"
+
+namespace kh {
+
+// ---- ranks (Sec. 3: r[v] ~ geometric(1/2), ties allowed) -----------------------------
+// SplitMix64's mixer (Steele, Lea, Flood, OOPSLA 2014); the rank counts the zero
+// bits before the first one bit of the word stream w_j = sm(sm(sm(seed)^v) ^ (sid<<32 | j)).
+__device__ __forceinline__ uint64_t sm64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_ranks(uint8_t* __restrict__ r, int32_t n, uint64_t seed, uint32_t sid) {
+    const uint64_t s0 = sm64(seed);
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint64_t base = sm64(s0 ^ (uint64_t)(int64_t)v);
+        int rank = 0;
+        int j = 0;
+        for (; j < 4; ++j) {
+            const uint64_t w = sm64(base ^ (((uint64_t)sid << 32) | (uint64_t)j));
+            if (w != 0ull) {
+                rank += __builtin_ctzll(w);
+                break;
+            }
+            rank += 64;
+        }
+        r[v] = (uint8_t)(rank > 255 ? 255 : rank);
+    }
+}
+
+void launch_ranks(uint8_t* r, int32_t n, uint64_t seed, uint32_t sid, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_ranks, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, r, n, seed, sid);
+}
+
+// ---- CSR validation on the device (simple undirected graph, Sec. 2) ---------------------
+// err bits: 1 row_ptr, 2 id out of range, 4 self-loop, 8 unsorted/duplicate, 16 asymmetric.
+__global__ void k_validate(const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t n, int64_t nnz,
+                           int* err) {
+    const int lanes = 64;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / lanes;
+    const int nwaves = gridDim.x * blockDim.x / lanes;
+    const int l = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (rp[0] != 0 || (int64_t)rp[n] != nnz) atomicOr(err, 1);
+    }
+    for (int32_t v = wave; v < n; v += nwaves) {
+        const int32_t a = rp[v], b = rp[v + 1];
+        if (a > b || a < 0 || (int64_t)b > nnz) {
+            if (l == 0) atomicOr(err, 1);
+            continue;
+        }
+        int e = 0;
+        for (int32_t p = a + l; p < b; p += lanes) {
+            const int32_t w = col[p];
+            if (w < 0 || w >= n) {
+                e |= 2;
+                continue;
+            }
+            if (w == v) e |= 4;
+            if (p > a && col[p - 1] >= w) e |= 8;
+            // symmetric: v must appear in the adjacency of w
+            int32_t lo = rp[w], hi = rp[w + 1];
+            if (lo < 0 || hi > nnz || lo > hi) {
+                e |= 1;
+                continue;
+            }
+            while (lo < hi) {
+                const int32_t mid = lo + ((hi - lo) >> 1);
+                if (col[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            if (lo >= rp[w + 1] || col[lo] != v) e |= 16;
+        }
+        for (int o = 32; o > 0; o >>= 1) e |= __shfl_xor(e, o);
+        if (l == 0 && e) atomicOr(err, e);
+    }
+}
+
+void launch_validate(const int32_t* rp, const int32_t* col, int32_t n, int64_t nnz, int* err, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_validate, dim3(grid_for((int64_t)n * 64, 256, 16384)), dim3(256), 0, s, rp, col, n, nnz,
+                       err);
+}
+
+// ---- fills (used instead of memset so the sequences can be graph-captured) ----------------
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, T v, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, v, count);
+}
+void launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, v, count);
+}
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, v, count);
+}
+void launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_fill<int64_t>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, v, count);
+}
+
+__global__ void k_alive_from(const uint8_t* __restrict__ src, uint8_t* __restrict__ alive, int32_t n) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        alive[v] = src ? (src[v] != 0) : 1;
+}
+void launch_alive_from(const uint8_t* src, uint8_t* alive, int32_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_alive_from, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, src, alive, n);
+}
+
+// Alive degree |A(v) ∩ X| (one wave per vertex).
+__global__ void k_alive_degree(const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               const uint8_t* __restrict__ alive, int32_t* __restrict__ adeg, int32_t n) {
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int l = lane_id();
+    for (int32_t v = wave; v < n; v += nwaves) {
+        int c = 0;
+        if (alive[v]) {
+            for (int32_t p = rp[v] + l; p < rp[v + 1]; p += 64) c += alive[col[p]] ? 1 : 0;
+            c = wave_sum_i(c);
+        }
+        if (l == 0) adeg[v] = c;
+    }
+}
+void launch_alive_degree(const int32_t* rp, const int32_t* col, const uint8_t* alive, int32_t* adeg, int32_t n,
+                         hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_alive_degree, dim3(grid_for((int64_t)n * 64, 256, 16384)), dim3(256), 0, s, rp, col,
+                           alive, adeg, n);
+}
+
+__global__ void k_compact_alive(const uint8_t* __restrict__ alive, int32_t n, int32_t* __restrict__ out, int* count) {
+    const int32_t stride = gridDim.x * blockDim.x;
+    // every lane of a wave runs the same trip count so the ballot is wave-wide
+    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int32_t v = base + threadIdx.x;
+        const bool want = v < n && alive[v];
+        const int slot = wave_append_slot(want, count);
+        if (want) out[slot] = v;
+    }
+}
+void launch_compact_alive(const uint8_t* alive, int32_t n, int32_t* out, int* count, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_compact_alive, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, alive, n, out, count);
+}
+
+// ---- round bookkeeping ------------------------------------------------------------------
+__global__ void k_round_reset(RoundState* st) {
+    st->min_key = LLONG_MAX;
+    st->sum_val = 0;
+    st->alive_count = 0;
+    st->rcount = 0;
+    st->stop = 0;
+    st->qcount = 0;
+    st->front_lo = 0;
+    st->front_hi = 0;
+    st->aff_fill = 0;
+    st->wl_count = 0;
+    st->changed_count[0] = 0;
+    st->changed_count[1] = 0;
+}
+void launch_round_reset(RoundState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, s, st);
+}
+
+// min of key, sum of val and count over alive vertices.
+__global__ void k_reduce(const int64_t* __restrict__ key, const int64_t* __restrict__ val,
+                         const uint8_t* __restrict__ alive, int32_t n, RoundState* st) {
+    long long mn = LLONG_MAX, sm = 0;
+    int cnt = 0;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        if (alive[v]) {
+            const long long k = key[v];
+            mn = k < mn ? k : mn;
+            sm += val ? val[v] : 0;
+            ++cnt;
+        }
+    }
+    mn = wave_min_ll(mn);
+    sm = wave_sum_ll(sm);
+    cnt = wave_sum_i(cnt);
+    if (lane_id() == 0 && cnt > 0) {
+        atomicMin(&st->min_key, mn);
+        atomicAdd((unsigned long long*)&st->sum_val, (unsigned long long)sm);
+        atomicAdd(&st->alive_count, cnt);
+    }
+}
+void launch_reduce(const int64_t* key, const int64_t* val, const uint8_t* alive, int32_t n, RoundState* st,
+                   hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_reduce, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, key, val, alive, n, st);
+}
+
+// c = max(c, min key).  When c rises to K, the alive set is exactly
+// F_K = {v : core(v) >= K} and sum_val is the sum of the values over it: that
+// is recorded as a densest-core candidate (Sec. 6).
+__global__ void k_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_size, int64_t* cand_sum, int early_stop) {
+    if (st->alive_count == 0) return;
+    long long c = st->c;
+    if (st->min_key > c) {
+        c = st->min_key;
+        if (cand_k) {
+            const int i = st->ncand;
+            cand_k[i] = c;
+            cand_size[i] = st->alive_count;
+            cand_sum[i] = st->sum_val;
+        }
+        st->ncand += 1;
+    }
+    st->c = c;
+    st->rounds += 1;
+    if (early_stop && c + 1 >= (long long)st->alive_count) st->stop = 1;
+}
+void launch_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_size, int64_t* cand_sum, int early_stop,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_round_begin, dim3(1), dim3(1), 0, s, st, cand_k, cand_size, cand_sum, early_stop);
+}
+
+// R = {alive v : key[v] <= c} (all alive when the early stop fired): core = c.
+__global__ void k_select(const int64_t* __restrict__ key, uint8_t* __restrict__ alive, int32_t n, RoundState* st,
+                         int64_t* __restrict__ core, int32_t* __restrict__ rlist, int32_t* __restrict__ mark,
+                         int32_t epoch, int kill) {
+    const long long c = st->c;
+    const int stop = st->stop;
+    const int32_t stride = gridDim.x * blockDim.x;
+    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int32_t v = base + threadIdx.x;
+        bool take = false;
+        if (v < n && alive[v]) take = stop || key[v] <= c;
+        const int slot = wave_append_slot(take, &st->rcount);
+        if (take) {
+            core[v] = c;
+            rlist[slot] = v;
+            if (mark) mark[v] = epoch;
+            if (kill) alive[v] = 0;
+        }
+    }
+}
+void launch_select(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core, int32_t* rlist,
+                   int32_t* mark, int32_t epoch, int kill, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_select, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, key, alive, n, st, core, rlist,
+                           mark, epoch, kill);
+}
+
+__global__ void k_kill_list(const int32_t* __restrict__ list, const int* count, uint8_t* __restrict__ alive) {
+    const int cnt = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) alive[list[i]] = 0;
+}
+void launch_kill_list(const int32_t* list, const int* count, uint8_t* alive, hipStream_t s) {
+    hipLaunchKernelGGL(k_kill_list, dim3(1024), dim3(256), 0, s, list, count, alive);
+}
+
+// ---- load-balanced frontier expansion ------------------------------------------------------
+// The adjacency of each listed vertex is cut into chunks of kExpandChunk arcs so
+// that hubs are spread over many waves.
+__global__ void k_enqueue(const int32_t* __restrict__ list, const int* lo_p, const int* hi_p,
+                          const int32_t* __restrict__ rp, int32_t* __restrict__ qv, int32_t* __restrict__ qb,
+                          int* qcount) {
+    const int lo = lo_p ? *lo_p : 0;
+    const int hi = *hi_p;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = lo + blockIdx.x * blockDim.x; base < hi; base += stride) {
+        const int i = base + threadIdx.x;
+        int v = 0, nch = 0;
+        if (i < hi) {
+            v = list[i];
+            const int d = rp[v + 1] - rp[v];
+            nch = (d + kExpandChunk - 1) / kExpandChunk;
+        }
+        const int incl = wave_incl_scan(nch);
+        const int total = __shfl(incl, 63);
+        int wbase = 0;
+        if (lane_id() == 63 && total > 0) wbase = atomicAdd(qcount, total);
+        wbase = __shfl(wbase, 63);
+        const int first = wbase + incl - nch;
+        for (int c = 0; c < nch; ++c) {
+            qv[first + c] = v;
+            qb[first + c] = rp[v] + c * kExpandChunk;
+        }
+    }
+}
+void launch_enqueue(const int32_t* list, const int* lo, const int* hi, const int32_t* rp, int32_t* qv, int32_t* qb,
+                    int* qcount, hipStream_t s) {
+    hipLaunchKernelGGL(k_enqueue, dim3(512), dim3(256), 0, s, list, lo, hi, rp, qv, qb, qcount);
+}
+
+__global__ void k_expand(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
+                         const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                         const uint8_t* __restrict__ alive, int32_t* __restrict__ mark, int32_t epoch, int mode,
+                         int32_t* __restrict__ out, int* out_count, int32_t* __restrict__ adeg) {
+    const int nq = *qcount;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int l = lane_id();
+    for (int q = wave; q < nq; q += nwaves) {
+        const int32_t v = qv[q];
+        const int32_t b = qb[q];
+        const int32_t e = min(b + kExpandChunk, rp[v + 1]);
+        for (int32_t p0 = b; p0 < e; p0 += 64) {
+            const int32_t p = p0 + l;
+            bool want = false;
+            int32_t w = 0;
+            if (p < e) {
+                w = col[p];
+                if (alive[w]) {
+                    if (mode == 0) {
+                        if (mark[w] != epoch) want = atomicExch(&mark[w], epoch) != epoch;
+                    } else {
+                        atomicSub(&adeg[w], 1);
+                    }
+                }
+            }
+            if (mode == 0) {
+                const int slot = wave_append_slot(want, out_count);
+                if (want) out[slot] = w;
+            }
+        }
+    }
+}
+void launch_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
+                   const uint8_t* alive, int32_t* mark, int32_t epoch, int mode, int32_t* out, int* out_count,
+                   int32_t* adeg, hipStream_t s) {
+    hipLaunchKernelGGL(k_expand, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, mark, epoch, mode, out,
+                       out_count, adeg);
+}
+
+__global__ void k_next_frontier(RoundState* st) {
+    st->front_lo = st->front_hi;
+    st->front_hi = st->aff_fill;
+    st->qcount = 0;
+}
+void launch_next_frontier(RoundState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_next_frontier, dim3(1), dim3(1), 0, s, st);
+}
+
+__global__ void k_level_reset(RoundState* st, int level) {
+    st->qcount = 0;
+    st->wl_count = 0;
+    st->changed_count[level & 1] = 0;
+}
+void launch_level_reset(RoundState* st, int level, hipStream_t s) {
+    hipLaunchKernelGGL(k_level_reset, dim3(1), dim3(1), 0, s, st, level);
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+void launch_set_int(int* p, int v, hipStream_t s) { hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v); }
+
+// ---- exclusive scan of int64 values: out[0] = 0, out[i+1] = sum in[0..i] -------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ long long block_excl_scan(long long v, long long* sh, long long* total) {
+    // sh holds kScanThreads/64 partial sums
+    const int l = lane_id();
+    const int w = threadIdx.x >> 6;
+    long long x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        long long t = __shfl_up(x, o);
+        if (l >= o) x += t;
+    }
+    if (l == 63) sh[w] = x;
+    __syncthreads();
+    long long off = 0, tot = 0;
+    for (int i = 0; i < kScanThreads / 64; ++i) {
+        if (i < w) off += sh[i];
+        tot += sh[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+__global__ void k_scan_partials(const int64_t* __restrict__ in, int32_t n, int64_t* __restrict__ partials) {
+    __shared__ long long sh[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    long long s = 0;
+    for (int i = 0; i < kScanItems; ++i)
+        if (base + i < n) s += in[base + i];
+    long long tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+__global__ void k_scan_top(int64_t* __restrict__ partials, int32_t nb) {
+    __shared__ long long sh[kScanThreads / 64];
+    long long carry = 0;
+    for (int32_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+        const int32_t i = b0 + threadIdx.x;
+        const long long v = i < nb ? partials[i] : 0;
+        long long tot;
+        const long long ex = block_excl_scan(v, sh, &tot);
+        if (i < nb) partials[i] = carry + ex;
+        carry += tot;
+    }
+}
+__global__ void k_scan_final(const int64_t* __restrict__ in, int64_t* __restrict__ out, int32_t n,
+                             const int64_t* __restrict__ partials) {
+    __shared__ long long sh[kScanThreads / 64];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    long long loc[kScanItems];
+    long long s = 0;
+    for (int i = 0; i < kScanItems; ++i) {
+        loc[i] = base + i < n ? in[base + i] : 0;
+        s += loc[i];
+    }
+    long long tot;
+    long long ex = block_excl_scan(s, sh, &tot) + partials[blockIdx.x];
+    for (int i = 0; i < kScanItems; ++i) {
+        if (base + i < n) out[base + i] = ex;
+        ex += loc[i];
+        if (base + i == n - 1) out[n] = ex;
+    }
+}
+void launch_scan_i64(const int64_t* in, int64_t* out, int32_t n, int64_t* partials, hipStream_t s) {
+    if (n <= 0) {
+        launch_fill_i64(out, 0, 1, s);
+        return;
+    }
+    const int nb = (int)((n + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kScanThreads), 0, s, in, n, partials);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
+    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanThreads), 0, s, in, out, n, partials);
+}
+
+__global__ void k_core_to_i32(const int64_t* __restrict__ core, int32_t* __restrict__ out, int32_t n, int* overflow) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int64_t c = core[v];
+        if (c > INT_MAX || c < INT_MIN) {
+            atomicOr(overflow, 1);
+            out[v] = INT_MAX;
+        } else {
+            out[v] = (int32_t)c;
+        }
+    }
+}
+void launch_core_to_i32(const int64_t* core, int32_t* out, int32_t n, int* overflow, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_core_to_i32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, core, out, n, overflow);
+}
+
+}  // namespace kh

@@ -1,0 +1,1085 @@
+// Host side of the C ABI declared in include/khcore.h: validation, residency,
+// the buffer size M, and the bulk peeling round loops that drive the kernels.
+//
+// Exact path (ExactCore, Sec. 2), one round:
+//   c <- max(c, min deg);  R = {alive v : deg[v] <= c};  core[R] = c;
+//   A = alive vertices within distance h of R in G[X] (1-bit BFS from R);
+//   X <- X \ R;  deg[A] <- h-degrees recomputed by the bit-parallel BFS.
+// Only vertices within distance h of a deleted vertex can change degree.
+//
+// Sampled path (Core, Alg. 4 with Update of Alg. 3), one round:
+//   c <- max(c, min d);  R = {alive v : d[v] <= c};  core'[R] = c;  X <- X \ R;
+//   for i = 1..h: recompute B[v,i] for the alive neighbours of R and of the
+//   vertices whose (k, B) changed at level i-1;  at i = h refresh d.
+// Deleting all of R at once gives the same numbers as Alg. 4's one-at-a-time
+// deletion: both keys only depend on (v, X) and never increase as X shrinks
+// (Prop. monotone for the estimate), so the running-maximum peel is the
+// maximal-core characterisation for every deletion order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <vector>
+
+#include "../../include/khcore.h"
+#include "kh_internal.hpp"
+
+using namespace kh;
+
+// ---------------------------------------------------------------------------------------------
+// errors and device memory
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+struct KhError {
+    kh_status code;
+};
+
+[[noreturn]] void fail(kh_status s) { throw KhError{s}; }
+
+void hip_ok(hipError_t e) {
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        fail(KH_ENOMEM);
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(KH_EDEVICE);
+    }
+}
+
+}  // namespace
+
+struct kh_context {
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    size_t lds_per_block = 65536;
+    int num_cu = 0;
+    RoundState* host_state = nullptr;  // pinned mirror of the device round state
+};
+
+namespace {
+
+template <typename T>
+struct Buf {
+    kh_context* ctx = nullptr;
+    T* p = nullptr;
+    size_t count = 0;
+    Buf() = default;
+    Buf(const Buf&) = delete;
+    Buf& operator=(const Buf&) = delete;
+    Buf(Buf&& o) noexcept : ctx(o.ctx), p(o.p), count(o.count) {
+        o.p = nullptr;
+        o.count = 0;
+    }
+    Buf& operator=(Buf&& o) noexcept {
+        if (this != &o) {
+            release();
+            ctx = o.ctx;
+            p = o.p;
+            count = o.count;
+            o.p = nullptr;
+            o.count = 0;
+        }
+        return *this;
+    }
+    ~Buf() { release(); }
+    void alloc(kh_context* c, size_t n) {
+        release();
+        ctx = c;
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        if (ctx->budget && ctx->used + bytes > ctx->budget) fail(KH_ENOMEM);
+        void* q = nullptr;
+        hip_ok(hipMalloc(&q, bytes));
+        p = static_cast<T*>(q);
+        count = n;
+        ctx->used += bytes;
+    }
+    void release() {
+        if (p) {
+            (void)hipFree(p);
+            ctx->used -= std::max<size_t>(count, 1) * sizeof(T);
+            p = nullptr;
+            count = 0;
+        }
+    }
+};
+
+int ceil_log2(long long x) {
+    int l = 0;
+    while ((1ll << l) < x) ++l;
+    return l;
+}
+
+}  // namespace
+
+struct kh_graph {
+    kh_context* ctx = nullptr;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    Buf<int32_t> rp_own, col_own;
+    const int32_t* rp = nullptr;
+    const int32_t* col = nullptr;
+    std::vector<int32_t> h_rp;
+    // work items of the h-degree pull kernel (built on first use)
+    bool items_built = false;
+    Buf<int32_t> it_u, it_beg, it_end, split_list;
+    Buf<uint8_t> it_split;
+    MsItems items{};
+};
+
+// ---------------------------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------------------------
+extern "C" const char* kh_status_str(kh_status s) {
+    switch (s) {
+        case KH_OK: return "KH_OK";
+        case KH_EINVAL: return "KH_EINVAL: invalid argument";
+        case KH_ENOMEM: return "KH_ENOMEM: out of device memory or HBM budget";
+        case KH_EDEVICE: return "KH_EDEVICE: GPU unavailable or HIP error";
+        case KH_EGRAPH: return "KH_EGRAPH: CSR is not a canonical simple undirected graph";
+        case KH_EOVERFLOW: return "KH_EOVERFLOW: value does not fit int32";
+        case KH_EBUSY: return "KH_EBUSY: request still running";
+        case KH_ENOTFOUND: return "KH_ENOTFOUND: unknown ticket";
+        case KH_ENOTIMPL: return "KH_ENOTIMPL: parameters outside what this build supports";
+        default: return "unknown kh_status";
+    }
+}
+
+// Eq. (buffer), Sec. 3: C = log(2n/delta) (Alg. 4) or log(n^2/delta) (Alg. 7).
+extern "C" int64_t kh_buffer_size(int64_t n, double epsilon, double delta, int32_t dense) {
+    if (n < 1 || !(epsilon > 0.0) || !(delta > 0.0 && delta < 1.0)) return -1;
+    const double C = dense ? std::log((double)n * (double)n / delta) : std::log(2.0 * (double)n / delta);
+    const double M = 1.0 + 4.0 * (2.0 + epsilon) / (epsilon * epsilon) * (C + std::log(8.0));
+    if (!(M < 9.0e18)) return INT64_MAX;
+    return (int64_t)std::floor(M);
+}
+
+extern "C" kh_status kh_validate_csr(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col) {
+    if (n < 0 || nnz < 0 || nnz > INT32_MAX) return KH_EINVAL;
+    if (!row_ptr || (nnz > 0 && !col)) return KH_EINVAL;
+    if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz) return KH_EGRAPH;
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+        if (a > b || a < 0 || (int64_t)b > nnz) return KH_EGRAPH;
+        for (int32_t p = a; p < b; ++p) {
+            const int32_t w = col[p];
+            if (w < 0 || w >= n || w == v) return KH_EGRAPH;
+            if (p > a && col[p - 1] >= w) return KH_EGRAPH;
+        }
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        for (int32_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) {
+            const int32_t w = col[p];
+            const int32_t* lo = col + row_ptr[w];
+            const int32_t* hi = col + row_ptr[w + 1];
+            const int32_t* it = std::lower_bound(lo, hi, v);
+            if (it == hi || *it != v) return KH_EGRAPH;
+        }
+    }
+    return KH_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// context and graphs
+// ---------------------------------------------------------------------------------------------
+extern "C" kh_status kh_context_create(int32_t device, uint64_t hbm_budget_bytes, kh_context** out) {
+    if (!out) return KH_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0 || device < 0 || device >= count) {
+        (void)hipGetLastError();
+        return KH_EDEVICE;
+    }
+    if (hipSetDevice(device) != hipSuccess) return KH_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return KH_EDEVICE;
+    auto* ctx = new (std::nothrow) kh_context();
+    if (!ctx) return KH_ENOMEM;
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    ctx->lds_per_block = prop.sharedMemPerBlock;
+    ctx->num_cu = prop.multiProcessorCount;
+    void* hs = nullptr;
+    if (hipHostMalloc(&hs, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
+        delete ctx;
+        return KH_EDEVICE;
+    }
+    ctx->host_state = static_cast<RoundState*>(hs);
+    *out = ctx;
+    return KH_OK;
+}
+
+extern "C" void kh_context_destroy(kh_context* ctx) {
+    if (!ctx) return;
+    if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+    delete ctx;
+}
+
+namespace {
+
+void canonicalize(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col, std::vector<int32_t>& rp,
+                  std::vector<int32_t>& cl) {
+    if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz) fail(KH_EGRAPH);
+    std::vector<std::pair<int32_t, int32_t>> arcs;
+    arcs.reserve((size_t)nnz * 2);
+    for (int32_t v = 0; v < n; ++v) {
+        if (row_ptr[v] > row_ptr[v + 1]) fail(KH_EGRAPH);
+        for (int32_t p = row_ptr[v]; p < row_ptr[v + 1]; ++p) {
+            const int32_t w = col[p];
+            if (w < 0 || w >= n) fail(KH_EGRAPH);
+            if (w == v) continue;
+            arcs.emplace_back(v, w);
+            arcs.emplace_back(w, v);
+        }
+    }
+    std::sort(arcs.begin(), arcs.end());
+    arcs.erase(std::unique(arcs.begin(), arcs.end()), arcs.end());
+    if (arcs.size() > (size_t)INT32_MAX) fail(KH_EINVAL);
+    rp.assign((size_t)n + 1, 0);
+    cl.resize(arcs.size());
+    for (size_t i = 0; i < arcs.size(); ++i) {
+        rp[arcs[i].first + 1]++;
+        cl[i] = arcs[i].second;
+    }
+    for (int32_t v = 0; v < n; ++v) rp[v + 1] += rp[v];
+}
+
+}  // namespace
+
+extern "C" kh_status kh_graph_load_csr(kh_context* ctx, int32_t n, int64_t nnz, const int32_t* row_ptr,
+                                       const int32_t* col, uint32_t flags, void* stream, kh_graph** out) {
+    if (!ctx || !out || n < 0 || nnz < 0 || nnz > INT32_MAX) return KH_EINVAL;
+    *out = nullptr;
+    if (!row_ptr || (nnz > 0 && !col)) return KH_EINVAL;
+    const bool borrow = (flags & KH_PTRS_DEVICE_BORROW) != 0;
+    if (borrow && (flags & KH_CANONICALIZE)) return KH_EINVAL;
+    auto s = static_cast<hipStream_t>(stream);
+    kh_graph* g = new (std::nothrow) kh_graph();
+    if (!g) return KH_ENOMEM;
+    try {
+        hip_ok(hipSetDevice(ctx->device));
+        g->ctx = ctx;
+        g->n = n;
+        if (!borrow) {
+            std::vector<int32_t> crp, ccol;
+            const int32_t* hrp = row_ptr;
+            const int32_t* hcol = col;
+            if (flags & KH_CANONICALIZE) {
+                canonicalize(n, nnz, row_ptr, col, crp, ccol);
+                hrp = crp.data();
+                hcol = ccol.data();
+                nnz = (int64_t)ccol.size();
+            } else if (!(flags & KH_TRUST_CSR)) {
+                const kh_status v = kh_validate_csr(n, nnz, row_ptr, col);
+                if (v != KH_OK) fail(v);
+            }
+            g->nnz = nnz;
+            g->h_rp.assign(hrp, hrp + (size_t)n + 1);
+            g->rp_own.alloc(ctx, (size_t)n + 1);
+            g->col_own.alloc(ctx, (size_t)std::max<int64_t>(nnz, 1));
+            hip_ok(hipMemcpyAsync(g->rp_own.p, hrp, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+            if (nnz > 0)
+                hip_ok(hipMemcpyAsync(g->col_own.p, hcol, sizeof(int32_t) * (size_t)nnz, hipMemcpyHostToDevice, s));
+            hip_ok(hipStreamSynchronize(s));
+            g->rp = g->rp_own.p;
+            g->col = g->col_own.p;
+        } else {
+            g->nnz = nnz;
+            g->rp = row_ptr;
+            g->col = col;
+            g->h_rp.resize((size_t)n + 1);
+            hip_ok(hipMemcpyAsync(g->h_rp.data(), row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost,
+                                  s));
+            hip_ok(hipStreamSynchronize(s));
+            if (!(flags & KH_TRUST_CSR) && n > 0) {
+                if (g->h_rp[0] != 0 || (int64_t)g->h_rp[n] != nnz) fail(KH_EGRAPH);
+                Buf<int> err;
+                err.alloc(ctx, 1);
+                launch_set_int(err.p, 0, s);
+                launch_validate(row_ptr, col, n, nnz, err.p, s);
+                int herr = 0;
+                hip_ok(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
+                hip_ok(hipStreamSynchronize(s));
+                if (herr) fail(KH_EGRAPH);
+            }
+        }
+    } catch (const KhError& e) {
+        delete g;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        delete g;
+        return KH_ENOMEM;
+    }
+    *out = g;
+    return KH_OK;
+}
+
+extern "C" void kh_graph_free(kh_graph* g) { delete g; }
+extern "C" int32_t kh_graph_n(const kh_graph* g) { return g ? g->n : -1; }
+extern "C" int64_t kh_graph_nnz(const kh_graph* g) { return g ? g->nnz : -1; }
+
+// ---------------------------------------------------------------------------------------------
+// engines
+// ---------------------------------------------------------------------------------------------
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+void check_params(const kh_graph* g, const kh_params* P) {
+    if (!g || !P) fail(KH_EINVAL);
+    if (P->h < 1) fail(KH_EINVAL);
+    if (!(P->delta > 0.0 && P->delta < 1.0)) fail(KH_EINVAL);
+    if (std::isnan(P->epsilon)) fail(KH_EINVAL);
+}
+
+// Work items of the pull kernel: (vertex, arc range) pieces of at most
+// kPullChunk arcs; split pieces first, then whole vertices by decreasing degree,
+// so that the groups of a wave see items of similar length.
+void build_items(kh_graph* g, hipStream_t s) {
+    if (g->items_built) return;
+    const int32_t n = g->n;
+    const std::vector<int32_t>& rp = g->h_rp;
+    std::vector<int32_t> iu, ib, ie, sl;
+    std::vector<uint8_t> isp;
+    int32_t maxd = 0;
+    for (int32_t v = 0; v < n; ++v) maxd = std::max(maxd, rp[v + 1] - rp[v]);
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t d = rp[v + 1] - rp[v];
+        if (d > kPullChunk) {
+            sl.push_back(v);
+            for (int32_t b = rp[v]; b < rp[v + 1]; b += kPullChunk) {
+                iu.push_back(v);
+                ib.push_back(b);
+                ie.push_back(std::min(b + kPullChunk, rp[v + 1]));
+                isp.push_back(1);
+            }
+        }
+    }
+    // counting sort of whole vertices by degree, descending
+    std::vector<int32_t> cnt((size_t)kPullChunk + 2, 0);
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t d = rp[v + 1] - rp[v];
+        if (d >= 1 && d <= kPullChunk) cnt[(size_t)d]++;
+    }
+    std::vector<int32_t> start((size_t)kPullChunk + 2, 0);
+    int32_t acc = 0;
+    for (int32_t d = kPullChunk; d >= 1; --d) {
+        start[(size_t)d] = acc;
+        acc += cnt[(size_t)d];
+    }
+    const size_t base = iu.size();
+    iu.resize(base + (size_t)acc);
+    ib.resize(base + (size_t)acc);
+    ie.resize(base + (size_t)acc);
+    isp.resize(base + (size_t)acc, 0);
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t d = rp[v + 1] - rp[v];
+        if (d >= 1 && d <= kPullChunk) {
+            const size_t at = base + (size_t)start[(size_t)d]++;
+            iu[at] = v;
+            ib[at] = rp[v];
+            ie[at] = rp[v + 1];
+        }
+    }
+    kh_context* ctx = g->ctx;
+    const size_t ni = iu.size();
+    g->it_u.alloc(ctx, ni);
+    g->it_beg.alloc(ctx, ni);
+    g->it_end.alloc(ctx, ni);
+    g->it_split.alloc(ctx, ni);
+    g->split_list.alloc(ctx, sl.size());
+    if (ni) {
+        hip_ok(hipMemcpyAsync(g->it_u.p, iu.data(), ni * 4, hipMemcpyHostToDevice, s));
+        hip_ok(hipMemcpyAsync(g->it_beg.p, ib.data(), ni * 4, hipMemcpyHostToDevice, s));
+        hip_ok(hipMemcpyAsync(g->it_end.p, ie.data(), ni * 4, hipMemcpyHostToDevice, s));
+        hip_ok(hipMemcpyAsync(g->it_split.p, isp.data(), ni, hipMemcpyHostToDevice, s));
+    }
+    if (!sl.empty()) hip_ok(hipMemcpyAsync(g->split_list.p, sl.data(), sl.size() * 4, hipMemcpyHostToDevice, s));
+    hip_ok(hipStreamSynchronize(s));
+    g->items.nitems = (int32_t)ni;
+    g->items.u = g->it_u.p;
+    g->items.beg = g->it_beg.p;
+    g->items.end = g->it_end.p;
+    g->items.split = g->it_split.p;
+    g->items.nsplit = (int32_t)sl.size();
+    g->items.split_list = g->split_list.p;
+    g->items_built = true;
+}
+
+// Bitset width per vertex (in 64-bit words): sources per batch = 64 Q.
+int pick_q(int64_t sources) {
+    int q = 1;
+    while (q < 16 && 64ll * q < sources) q <<= 1;
+    return q;
+}
+
+struct Planes {
+    Buf<uint64_t> vis, frA, frB, acc, valid;
+    Buf<uint32_t> bmA, bmB, bmT, cnt;
+    Buf<int32_t> touched;
+    Buf<int> tcount;
+    int qmax = 0;
+    void alloc(kh_context* ctx, int32_t n, int qmax_) {
+        qmax = qmax_;
+        const size_t words = (size_t)std::max(n, 1) * qmax;
+        const size_t bm = ((size_t)std::max(n, 1) + 31) / 32;
+        vis.alloc(ctx, words);
+        frA.alloc(ctx, words);
+        frB.alloc(ctx, words);
+        acc.alloc(ctx, words);
+        valid.alloc(ctx, 16);
+        bmA.alloc(ctx, bm);
+        bmB.alloc(ctx, bm);
+        bmT.alloc(ctx, bm);
+        cnt.alloc(ctx, 64 * 16);
+        touched.alloc(ctx, (size_t)std::max(n, 1));
+        tcount.alloc(ctx, 1);
+    }
+    void clear(hipStream_t s) {
+        hip_ok(hipMemsetAsync(vis.p, 0, vis.count * 8, s));
+        hip_ok(hipMemsetAsync(acc.p, 0, acc.count * 8, s));
+        hip_ok(hipMemsetAsync(cnt.p, 0, cnt.count * 4, s));
+    }
+    MsPlanes view(int q) const {
+        MsPlanes P;
+        P.Q = q;
+        P.vis = vis.p;
+        P.frA = frA.p;
+        P.frB = frB.p;
+        P.acc = acc.p;
+        P.bmA = bmA.p;
+        P.bmB = bmB.p;
+        P.bmT = bmT.p;
+        P.touched = touched.p;
+        P.touched_count = tcount.p;
+        P.cnt = cnt.p;
+        P.valid = valid.p;
+        return P;
+    }
+};
+
+// h-degrees of every vertex in `src[0..count)` (device list, host count).
+void hdeg_sources(kh_graph* g, Planes& PL, const uint8_t* alive, const int32_t* adeg, const int32_t* src, int64_t count,
+                  int h, int64_t* deg, RoundState* st, hipStream_t s) {
+    int64_t done = 0;
+    while (done < count) {
+        const int64_t rest = count - done;
+        const int q = std::min(PL.qmax, pick_q(rest));
+        const int ns = (int)std::min<int64_t>(rest, 64ll * q);
+        ms_batch(PL.view(q), g->items, g->n, g->rp, g->col, alive, adeg, src + done, ns, h, deg, st, s);
+        done += ns;
+    }
+}
+
+void read_state(kh_context* ctx, RoundState* dst_dev, hipStream_t s) {
+    hip_ok(hipGetLastError());
+    hip_ok(hipMemcpyAsync(ctx->host_state, dst_dev, sizeof(RoundState), hipMemcpyDeviceToHost, s));
+    hip_ok(hipStreamSynchronize(s));
+}
+
+void init_state(RoundState* st, hipStream_t s) {
+    RoundState z;
+    std::memset(&z, 0, sizeof(z));
+    z.c = -1;
+    hip_ok(hipMemcpyAsync(st, &z, sizeof(z), hipMemcpyHostToDevice, s));
+    hip_ok(hipStreamSynchronize(s));
+}
+
+struct Candidates {
+    std::vector<int64_t> k, size, sum;
+};
+
+void pick_dense(const Candidates& C, bool prune, double eps, int64_t maxcore, kh_result* res) {
+    int64_t bk = -1, bs = 0, bR = 0;
+    const double e = eps > 0.0 ? std::min(eps, 0.999999) : 0.0;
+    for (size_t i = 0; i < C.k.size(); ++i) {
+        const int64_t K = C.k[i];
+        if (prune && (double)K * (1.0 + e) < (1.0 - e) * (double)maxcore) continue;
+        const int64_t S = C.size[i], R = C.sum[i];
+        if (bk < 0 || (__int128)R * (__int128)bs >= (__int128)bR * (__int128)S) {
+            bk = K;
+            bs = S;
+            bR = R;
+        }
+    }
+    res->dense_k = bk;
+    res->dense_size = bs;
+    res->dense_R = bR;
+    res->dense_density = bs > 0 ? (double)bR / (2.0 * (double)bs) : 0.0;
+}
+
+Candidates read_candidates(const RoundState& hs, const Buf<int64_t>& ck, const Buf<int64_t>& cs,
+                           const Buf<int64_t>& cr, hipStream_t s) {
+    Candidates C;
+    const size_t nc = (size_t)hs.ncand;
+    C.k.resize(nc);
+    C.size.resize(nc);
+    C.sum.resize(nc);
+    if (nc) {
+        hip_ok(hipMemcpyAsync(C.k.data(), ck.p, nc * 8, hipMemcpyDeviceToHost, s));
+        hip_ok(hipMemcpyAsync(C.size.data(), cs.p, nc * 8, hipMemcpyDeviceToHost, s));
+        hip_ok(hipMemcpyAsync(C.sum.data(), cr.p, nc * 8, hipMemcpyDeviceToHost, s));
+        hip_ok(hipStreamSynchronize(s));
+    }
+    return C;
+}
+
+// ----- exact engine ---------------------------------------------------------------------------
+// key == nullptr: ExactCore peel (key = deg).  Otherwise a replay whose rounds
+// delete by the given key (a core map), used for the densest-core sums.
+struct ExactRun {
+    kh_graph* g;
+    int h;
+    hipStream_t s;
+    Buf<uint8_t> alive;
+    Buf<int32_t> adeg, mark, rlist, alist, qv, qb, srcl;
+    Buf<int64_t> deg, core, ck, cs, cr;
+    Buf<RoundState> st;
+    Planes PL;
+    Candidates cands;
+    RoundState fin{};
+
+    void run(const uint8_t* alive_in, const int64_t* key_ext) {
+        kh_context* ctx = g->ctx;
+        const int32_t n = g->n;
+        build_items(g, s);
+        alive.alloc(ctx, n);
+        adeg.alloc(ctx, n);
+        mark.alloc(ctx, n);
+        rlist.alloc(ctx, n);
+        alist.alloc(ctx, n);
+        srcl.alloc(ctx, n);
+        const size_t qcap = (size_t)n + (size_t)(g->nnz / kExpandChunk) + 2;
+        qv.alloc(ctx, qcap);
+        qb.alloc(ctx, qcap);
+        deg.alloc(ctx, n);
+        core.alloc(ctx, n);
+        ck.alloc(ctx, (size_t)n + 1);
+        cs.alloc(ctx, (size_t)n + 1);
+        cr.alloc(ctx, (size_t)n + 1);
+        st.alloc(ctx, 1);
+        PL.alloc(ctx, n, pick_q(n));
+        PL.clear(s);
+        init_state(st.p, s);
+        launch_alive_from(alive_in, alive.p, n, s);
+        launch_alive_degree(g->rp, g->col, alive.p, adeg.p, n, s);
+        launch_fill_i32(mark.p, 0, n, s);
+        launch_fill_i64(deg.p, 0, n, s);
+        launch_fill_i64(core.p, -1, n, s);
+        // initial h-degrees of every alive vertex
+        launch_round_reset(st.p, s);
+        launch_compact_alive(alive.p, n, srcl.p, &st.p->aff_fill, s);
+        read_state(ctx, st.p, s);
+        hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, ctx->host_state->aff_fill, h, deg.p, st.p, s);
+        const int64_t* key = key_ext ? key_ext : deg.p;
+        int32_t epoch = 0;
+        for (;;) {
+            ++epoch;
+            launch_round_reset(st.p, s);
+            launch_reduce(key, deg.p, alive.p, n, st.p, s);
+            launch_round_begin(st.p, ck.p, cs.p, cr.p, 0, s);
+            launch_select(key, alive.p, n, st.p, core.p, rlist.p, mark.p, epoch, 0, s);
+            // vertices within distance h of R in G[X] (R still alive here)
+            launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
+            launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 0, alist.p,
+                          &st.p->aff_fill, nullptr, s);
+            for (int t = 2; t <= h; ++t) {
+                launch_next_frontier(st.p, s);
+                launch_enqueue(alist.p, &st.p->front_lo, &st.p->front_hi, g->rp, qv.p, qb.p, &st.p->qcount, s);
+                launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 0, alist.p,
+                              &st.p->aff_fill, nullptr, s);
+            }
+            launch_kill_list(rlist.p, &st.p->rcount, alive.p, s);
+            launch_set_int(&st.p->qcount, 0, s);
+            launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
+            launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 1, nullptr, nullptr,
+                          adeg.p, s);
+            read_state(ctx, st.p, s);
+            const RoundState hs = *ctx->host_state;
+            if (hs.alive_count == 0) break;
+            // every round deletes at least the minimum vertex
+            if (hs.rounds > n + 1) fail(KH_EDEVICE);
+            if (hs.aff_fill > 0) hdeg_sources(g, PL, alive.p, adeg.p, alist.p, hs.aff_fill, h, deg.p, st.p, s);
+        }
+        fin = *ctx->host_state;
+        cands = read_candidates(fin, ck, cs, cr, s);
+    }
+};
+
+// ----- sampled engine ---------------------------------------------------------------------------
+struct Lists {
+    int h = 0;
+    int32_t M = 0;
+    int hash_log2 = 9;
+    std::vector<Buf<int64_t>> cap, off;
+    std::vector<Buf<uint32_t>> keys;
+    std::vector<Buf<int32_t>> size;
+    std::vector<Buf<uint8_t>> kk;
+    std::vector<int64_t> total;
+};
+
+int hash_log2_for(int32_t M) { return std::max(9, ceil_log2(2ll * ((long long)M + 1 + kUnionThreads))); }
+
+int32_t max_sampled_M(const kh_context* ctx) {
+    // dynamic LDS of the union kernel: 4 << hash_log2 bytes, plus ~1.1 KiB static
+    int l = 9;
+    while (l < 20 && ((size_t)4 << (l + 1)) + 2048 <= ctx->lds_per_block) ++l;
+    return (int32_t)((1ll << (l - 1)) - 1 - kUnionThreads);
+}
+
+struct SampledRun {
+    kh_graph* g;
+    int h;
+    int32_t M;
+    uint64_t seed;
+    uint32_t stream_id;
+    bool early_stop = false;
+    hipStream_t s;
+    Buf<uint8_t> alive, rank;
+    Buf<int32_t> mark, rlist, wl, chA, chB, qv, qb, cursor;
+    Buf<int64_t> d, core, ck, cs, cr, partials;
+    Buf<RoundState> st;
+    Lists L;
+    Candidates cands;
+    RoundState fin{};
+
+    void alloc_common() {
+        kh_context* ctx = g->ctx;
+        const int32_t n = g->n;
+        alive.alloc(ctx, n);
+        rank.alloc(ctx, n);
+        mark.alloc(ctx, n);
+        rlist.alloc(ctx, n);
+        wl.alloc(ctx, n);
+        chA.alloc(ctx, n);
+        chB.alloc(ctx, n);
+        const size_t qcap = (size_t)n + (size_t)(g->nnz / kExpandChunk) + 2;
+        qv.alloc(ctx, qcap);
+        qb.alloc(ctx, qcap);
+        cursor.alloc(ctx, (size_t)std::max<int64_t>(g->nnz, 1));
+        d.alloc(ctx, n);
+        core.alloc(ctx, n);
+        ck.alloc(ctx, (size_t)n + 1);
+        cs.alloc(ctx, (size_t)n + 1);
+        cr.alloc(ctx, (size_t)n + 1);
+        partials.alloc(ctx, (size_t)n / 2048 + 2);
+        st.alloc(ctx, 1);
+    }
+
+    void build_lists() {
+        kh_context* ctx = g->ctx;
+        const int32_t n = g->n;
+        L.h = h;
+        L.M = M;
+        L.hash_log2 = hash_log2_for(M);
+        L.cap.resize(h + 1);
+        L.off.resize(h + 1);
+        L.keys.resize(h + 1);
+        L.size.resize(h + 1);
+        L.kk.resize(h + 1);
+        L.total.assign(h + 1, 0);
+        for (int i = 1; i <= h; ++i) {
+            L.cap[i].alloc(ctx, n);
+            L.off[i].alloc(ctx, (size_t)n + 1);
+            if (i == 1)
+                launch_cap_level1(g->rp, n, M, L.cap[i].p, s);
+            else
+                launch_cap_next(g->rp, g->col, n, M, L.cap[i - 1].p, L.cap[i].p, s);
+            launch_scan_i64(L.cap[i].p, L.off[i].p, n, partials.p, s);
+            int64_t tot = 0;
+            hip_ok(hipMemcpyAsync(&tot, L.off[i].p + n, 8, hipMemcpyDeviceToHost, s));
+            hip_ok(hipStreamSynchronize(s));
+            L.total[i] = tot;
+            L.keys[i].alloc(ctx, (size_t)std::max<int64_t>(tot, 1));
+            L.size[i].alloc(ctx, n);
+            L.kk[i].alloc(ctx, n);
+        }
+        for (int i = 1; i < h; ++i) L.cap[i].release();
+        if (h >= 1) L.cap[h].release();
+    }
+
+    void init_lists() {
+        const int32_t n = g->n;
+        launch_union1(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.off[1].p, L.keys[1].p, L.size[1].p,
+                      L.kk[1].p, nullptr, nullptr, st.p, s);
+        for (int i = 2; i <= h; ++i)
+            launch_union(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2, L.off[i - 1].p,
+                         L.keys[i - 1].p, L.size[i - 1].p, L.kk[i - 1].p, L.off[i].p, L.keys[i].p, L.size[i].p,
+                         L.kk[i].p, cursor.p, nullptr, nullptr, st.p, s);
+        launch_estimate(nullptr, nullptr, n, alive.p, rank.p, L.size[h].p, L.kk[h].p, M, d.p, st.p, s);
+    }
+
+    void setup(const uint8_t* alive_in) {
+        alloc_common();
+        init_state(st.p, s);
+        launch_alive_from(alive_in, alive.p, g->n, s);
+        launch_ranks(rank.p, g->n, seed, stream_id, s);
+        launch_fill_i32(mark.p, 0, g->n, s);
+        launch_fill_i64(core.p, -1, g->n, s);
+        launch_fill_i64(d.p, 0, g->n, s);
+        build_lists();
+        init_lists();
+    }
+
+    // Alg. 4's deletion loop in bulk rounds.  key == nullptr: delete by the
+    // estimate d (Core).  Otherwise delete by the given core map (the replay of
+    // Alg. 7) and record sum d at every level.
+    void peel(const int64_t* key_ext) {
+        kh_context* ctx = g->ctx;
+        const int32_t n = g->n;
+        const int64_t* key = key_ext ? key_ext : d.p;
+        int32_t* changed[2] = {chA.p, chB.p};
+        int32_t epoch = 0;
+        const int batch = 8;
+        for (;;) {
+            for (int r = 0; r < batch; ++r) {
+                launch_round_reset(st.p, s);
+                launch_reduce(key, d.p, alive.p, n, st.p, s);
+                launch_round_begin(st.p, ck.p, cs.p, cr.p, early_stop ? 1 : 0, s);
+                launch_select(key, alive.p, n, st.p, core.p, rlist.p, nullptr, 0, 1, s);
+                for (int i = 1; i <= h; ++i) {
+                    ++epoch;
+                    launch_level_reset(st.p, i, s);
+                    launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
+                    if (i > 1)
+                        launch_enqueue(changed[(i - 1) & 1], nullptr, &st.p->changed_count[(i - 1) & 1], g->rp, qv.p,
+                                       qb.p, &st.p->qcount, s);
+                    launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 0, wl.p,
+                                  &st.p->wl_count, nullptr, s);
+                    if (i == 1)
+                        launch_union1(wl.p, &st.p->wl_count, n, g->rp, g->col, alive.p, rank.p, M, L.off[1].p,
+                                      L.keys[1].p, L.size[1].p, L.kk[1].p, changed[1], &st.p->changed_count[1], st.p,
+                                      s);
+                    else
+                        launch_union(wl.p, &st.p->wl_count, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2,
+                                     L.off[i - 1].p, L.keys[i - 1].p, L.size[i - 1].p, L.kk[i - 1].p, L.off[i].p,
+                                     L.keys[i].p, L.size[i].p, L.kk[i].p, cursor.p, changed[i & 1],
+                                     &st.p->changed_count[i & 1], st.p, s);
+                }
+                launch_estimate(changed[h & 1], &st.p->changed_count[h & 1], n, alive.p, rank.p, L.size[h].p,
+                                L.kk[h].p, M, d.p, st.p, s);
+            }
+            read_state(ctx, st.p, s);
+            if (ctx->host_state->alive_count == 0) break;
+            // every round deletes at least the minimum vertex
+            if (ctx->host_state->rounds > n + 1) fail(KH_EDEVICE);
+        }
+        fin = *ctx->host_state;
+        cands = read_candidates(fin, ck, cs, cr, s);
+    }
+};
+
+void finish_core(kh_context* ctx, const int64_t* core64, int32_t n, int32_t* core_out, bool out_dev, hipStream_t s,
+                 int32_t* max_core) {
+    Buf<int32_t> tmp;
+    Buf<int> ovf;
+    ovf.alloc(ctx, 1);
+    launch_set_int(ovf.p, 0, s);
+    int32_t* dst = core_out;
+    if (!out_dev) {
+        tmp.alloc(ctx, n);
+        dst = tmp.p;
+    }
+    launch_core_to_i32(core64, dst, n, ovf.p, s);
+    int hovf = 0;
+    hip_ok(hipMemcpyAsync(&hovf, ovf.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    if (!out_dev) hip_ok(hipMemcpyAsync(core_out, tmp.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+    hip_ok(hipStreamSynchronize(s));
+    if (hovf) fail(KH_EOVERFLOW);
+    if (max_core) {
+        int32_t m = 0;
+        if (!out_dev) {
+            for (int32_t v = 0; v < n; ++v) m = std::max(m, core_out[v]);
+        } else {
+            std::vector<int32_t> h(n);
+            hip_ok(hipMemcpyAsync(h.data(), core_out, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+            hip_ok(hipStreamSynchronize(s));
+            for (int32_t v = 0; v < n; ++v) m = std::max(m, h[v]);
+        }
+        *max_core = m;
+    }
+}
+
+int32_t resolve_M(const kh_graph* g, const kh_params* P, bool dense) {
+    const int32_t ov = dense ? P->M_dense_override : P->M_override;
+    int64_t M = ov > 0 ? ov : kh_buffer_size(std::max<int64_t>(g->n, 1), P->epsilon, P->delta, dense ? 1 : 0);
+    if (M < 1) fail(KH_EINVAL);
+    if (M > max_sampled_M(g->ctx)) fail(KH_ENOTIMPL);
+    return (int32_t)M;
+}
+
+int effective_h(const kh_graph* g, int h) {
+    // N(v;h,X) is the whole component once h >= |X| - 1
+    const int64_t cap = std::max<int64_t>((int64_t)g->n - 1, 1);
+    return (int)std::min<int64_t>(h, cap);
+}
+
+// Densest core level of a core map given on the device (Sec. 6 / Alg. 7).
+void dense_sampled(kh_graph* g, const kh_params* P, const int64_t* core_dev, int64_t maxcore, kh_result* res,
+                   hipStream_t s) {
+    const int h = effective_h(g, P->h);
+    const bool prune = (P->flags & KH_DENSE_PRUNE) != 0;
+    SampledRun R;
+    R.g = g;
+    R.h = h;
+    R.M = resolve_M(g, P, true);
+    R.seed = P->seed;
+    R.stream_id = 1;
+    R.s = s;
+    Buf<uint8_t> start;
+    const uint8_t* alive_in = nullptr;
+    if (prune) {
+        // only levels K with K (1 + eps) >= (1 - eps) max core take part
+        std::vector<int64_t> hc((size_t)g->n);
+        hip_ok(hipMemcpyAsync(hc.data(), core_dev, 8 * (size_t)g->n, hipMemcpyDeviceToHost, s));
+        hip_ok(hipStreamSynchronize(s));
+        const double e = std::min(std::max(P->epsilon, 0.0), 0.999999);
+        std::vector<uint8_t> a((size_t)g->n);
+        for (int32_t v = 0; v < g->n; ++v) a[v] = (double)hc[v] * (1.0 + e) >= (1.0 - e) * (double)maxcore;
+        start.alloc(g->ctx, g->n);
+        hip_ok(hipMemcpyAsync(start.p, a.data(), (size_t)g->n, hipMemcpyHostToDevice, s));
+        alive_in = start.p;
+    }
+    R.setup(alive_in);
+    R.peel(core_dev);
+    pick_dense(R.cands, prune, P->epsilon, maxcore, res);
+    res->M_dense_used = R.M;
+    res->list_elements += (int64_t)R.fin.elems;
+}
+
+void dense_exact(kh_graph* g, const kh_params* P, const int64_t* core_dev, int64_t maxcore, kh_result* res,
+                 hipStream_t s) {
+    ExactRun E;
+    E.g = g;
+    E.h = effective_h(g, P->h);
+    E.s = s;
+    E.run(nullptr, core_dev);
+    pick_dense(E.cands, (P->flags & KH_DENSE_PRUNE) != 0, 0.0, maxcore, res);
+    res->edges_traversed += (int64_t)E.fin.te;
+    res->arcs_scanned += (int64_t)E.fin.arcs;
+}
+
+void clear_result(kh_result* r) {
+    std::memset(r, 0, sizeof(*r));
+    r->dense_k = -1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// the hot path
+// ---------------------------------------------------------------------------------------------
+extern "C" kh_status kh_core(kh_graph* g, const kh_params* P, int32_t* core_out, kh_result* res, void* stream) {
+    const auto t0 = Clock::now();
+    kh_result local;
+    kh_result* R = res ? res : &local;
+    clear_result(R);
+    try {
+        check_params(g, P);
+        if (g->n > 0 && !core_out) fail(KH_EINVAL);
+        hip_ok(hipSetDevice(g->ctx->device));
+        auto s = static_cast<hipStream_t>(stream);
+        const bool out_dev = (P->flags & KH_OUT_DEVICE) != 0;
+        const bool want_dense = (P->flags & KH_WANT_DENSE) != 0;
+        if (g->n == 0) {
+            R->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+            return KH_OK;
+        }
+        const int h = effective_h(g, P->h);
+        if (P->epsilon <= 0.0) {
+            ExactRun E;
+            E.g = g;
+            E.h = h;
+            E.s = s;
+            E.run(nullptr, nullptr);
+            finish_core(g->ctx, E.core.p, g->n, core_out, out_dev, s, &R->max_core);
+            R->rounds = E.fin.rounds;
+            R->edges_traversed = (int64_t)E.fin.te;
+            R->arcs_scanned = (int64_t)E.fin.arcs;
+            if (want_dense) pick_dense(E.cands, (P->flags & KH_DENSE_PRUNE) != 0, 0.0, R->max_core, R);
+        } else {
+            if (g->n > kMaxSampledN) fail(KH_ENOTIMPL);
+            SampledRun S;
+            S.g = g;
+            S.h = h;
+            S.M = resolve_M(g, P, false);
+            S.seed = P->seed;
+            S.stream_id = 0;
+            S.early_stop = (P->flags & KH_EARLY_STOP) != 0;
+            S.s = s;
+            S.setup(nullptr);
+            S.peel(nullptr);
+            if (S.fin.overflow) fail(KH_EOVERFLOW);
+            finish_core(g->ctx, S.core.p, g->n, core_out, out_dev, s, &R->max_core);
+            R->M_used = S.M;
+            R->rounds = S.fin.rounds;
+            R->list_elements = (int64_t)S.fin.elems;
+            if (want_dense) {
+                // free the core pass's lists before the dense pass allocates its own
+                for (auto& k : S.L.keys) k.release();
+                dense_sampled(g, P, S.core.p, R->max_core, R, s);
+            }
+        }
+    } catch (const KhError& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return KH_ENOMEM;
+    }
+    R->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+    return KH_OK;
+}
+
+extern "C" kh_status kh_hdeg(kh_graph* g, int32_t h, const uint8_t* alive_in, uint32_t flags, int32_t* deg_out,
+                             int64_t* edges_traversed, void* stream) {
+    try {
+        if (!g || h < 1) fail(KH_EINVAL);
+        if (g->n > 0 && !deg_out) fail(KH_EINVAL);
+        if (g->n == 0) return KH_OK;
+        hip_ok(hipSetDevice(g->ctx->device));
+        auto s = static_cast<hipStream_t>(stream);
+        kh_context* ctx = g->ctx;
+        const int32_t n = g->n;
+        const int he = effective_h(g, h);
+        build_items(g, s);
+        Buf<uint8_t> alive;
+        Buf<int32_t> adeg, srcl;
+        Buf<int64_t> deg, core;
+        Buf<RoundState> st;
+        Planes PL;
+        alive.alloc(ctx, n);
+        adeg.alloc(ctx, n);
+        srcl.alloc(ctx, n);
+        deg.alloc(ctx, n);
+        st.alloc(ctx, 1);
+        PL.alloc(ctx, n, pick_q(n));
+        PL.clear(s);
+        init_state(st.p, s);
+        launch_alive_from(alive_in, alive.p, n, s);
+        launch_alive_degree(g->rp, g->col, alive.p, adeg.p, n, s);
+        launch_fill_i64(deg.p, -1, n, s);
+        launch_round_reset(st.p, s);
+        launch_compact_alive(alive.p, n, srcl.p, &st.p->aff_fill, s);
+        read_state(ctx, st.p, s);
+        hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, ctx->host_state->aff_fill, he, deg.p, st.p, s);
+        finish_core(ctx, deg.p, n, deg_out, (flags & KH_OUT_DEVICE) != 0, s, nullptr);
+        read_state(ctx, st.p, s);
+        if (edges_traversed) *edges_traversed = (int64_t)ctx->host_state->te;
+    } catch (const KhError& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return KH_ENOMEM;
+    }
+    return KH_OK;
+}
+
+extern "C" kh_status kh_ranks(kh_context* ctx, int32_t n, uint64_t seed, uint32_t stream_id, uint8_t* r_out,
+                              void* stream) {
+    if (!ctx || n < 0 || (n > 0 && !r_out)) return KH_EINVAL;
+    try {
+        hip_ok(hipSetDevice(ctx->device));
+        auto s = static_cast<hipStream_t>(stream);
+        launch_ranks(r_out, n, seed, stream_id, s);
+        hip_ok(hipGetLastError());
+    } catch (const KhError& e) {
+        return e.code;
+    }
+    return KH_OK;
+}
+
+extern "C" kh_status kh_sampled_lists(kh_graph* g, const kh_params* P, const uint8_t* alive_in, int32_t level,
+                                      int32_t* k_out, int32_t* size_out, int32_t* members_out, int64_t members_cap,
+                                      int64_t* est_out, void* stream) {
+    try {
+        check_params(g, P);
+        if (!(P->epsilon > 0.0) && P->M_override <= 0) fail(KH_EINVAL);
+        if (level < 1 || level > P->h) fail(KH_EINVAL);
+        if (g->n > 0 && (!k_out || !size_out)) fail(KH_EINVAL);
+        if (g->n == 0) return KH_OK;
+        if (g->n > kMaxSampledN) fail(KH_ENOTIMPL);
+        hip_ok(hipSetDevice(g->ctx->device));
+        auto s = static_cast<hipStream_t>(stream);
+        const int32_t n = g->n;
+        SampledRun S;
+        S.g = g;
+        S.h = P->h;
+        S.M = resolve_M(g, P, false);
+        S.seed = P->seed;
+        S.stream_id = 0;
+        S.s = s;
+        S.setup(alive_in);
+        std::vector<uint8_t> ha((size_t)n), hk((size_t)n);
+        std::vector<int32_t> hs((size_t)n);
+        std::vector<int64_t> ho((size_t)n + 1);
+        hip_ok(hipMemcpyAsync(ha.data(), S.alive.p, (size_t)n, hipMemcpyDeviceToHost, s));
+        hip_ok(hipMemcpyAsync(hk.data(), S.L.kk[level].p, (size_t)n, hipMemcpyDeviceToHost, s));
+        hip_ok(hipMemcpyAsync(hs.data(), S.L.size[level].p, 4 * (size_t)n, hipMemcpyDeviceToHost, s));
+        hip_ok(hipMemcpyAsync(ho.data(), S.L.off[level].p, 8 * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+        std::vector<uint32_t> hkeys((size_t)std::max<int64_t>(S.L.total[level], 1));
+        hip_ok(hipMemcpyAsync(hkeys.data(), S.L.keys[level].p, 4 * (size_t)S.L.total[level], hipMemcpyDeviceToHost, s));
+        if (est_out) hip_ok(hipMemcpyAsync(est_out, S.d.p, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+        hip_ok(hipStreamSynchronize(s));
+        int64_t total = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            if (!ha[v]) {
+                k_out[v] = -1;
+                size_out[v] = 0;
+                if (est_out) est_out[v] = -1;
+                continue;
+            }
+            k_out[v] = hk[v];
+            size_out[v] = hs[v];
+            if (members_out) {
+                if (total + hs[v] > members_cap) fail(KH_EINVAL);
+                int32_t* dst = members_out + total;
+                for (int32_t i = 0; i < hs[v]; ++i) dst[i] = (int32_t)(hkeys[(size_t)ho[v] + i] & 0xFFFFFFu);
+                std::sort(dst, dst + hs[v]);
+            }
+            total += hs[v];
+        }
+    } catch (const KhError& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return KH_ENOMEM;
+    }
+    return KH_OK;
+}
+
+extern "C" kh_status kh_dense(kh_graph* g, const kh_params* P, const int32_t* core_in, kh_result* res, void* stream) {
+    try {
+        check_params(g, P);
+        if (!res || (g->n > 0 && !core_in)) fail(KH_EINVAL);
+        clear_result(res);
+        if (g->n == 0) return KH_OK;
+        hip_ok(hipSetDevice(g->ctx->device));
+        auto s = static_cast<hipStream_t>(stream);
+        const int32_t n = g->n;
+        std::vector<int64_t> hc((size_t)n);
+        int64_t maxcore = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            if (core_in[v] < 0) fail(KH_EINVAL);
+            hc[v] = core_in[v];
+            maxcore = std::max<int64_t>(maxcore, hc[v]);
+        }
+        Buf<int64_t> cd;
+        cd.alloc(g->ctx, n);
+        hip_ok(hipMemcpyAsync(cd.p, hc.data(), 8 * (size_t)n, hipMemcpyHostToDevice, s));
+        if (P->epsilon <= 0.0) {
+            dense_exact(g, P, cd.p, maxcore, res, s);
+        } else {
+            if (n > kMaxSampledN) fail(KH_ENOTIMPL);
+            dense_sampled(g, P, cd.p, maxcore, res, s);
+        }
+    } catch (const KhError& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return KH_ENOMEM;
+    }
+    return KH_OK;
+}

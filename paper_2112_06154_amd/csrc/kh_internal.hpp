@@ -1,0 +1,141 @@
+// Internal declarations shared by the kernels (*.hip) and the host
+// orchestration (kh_host.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kh {
+
+// ---- sizes --------------------------------------------------------------------
+
+// Arcs per work item of the h-degree pull kernel; vertices with more arcs are
+// split across several items whose partial ORs meet in an accumulator plane.
+constexpr int kPullChunk = 128;
+// Arcs per chunk of the frontier-expansion kernels.
+constexpr int kExpandChunk = 256;
+// Sampled lists store 32-bit keys ((255 - rank) << 24 | id): ascending key
+// order is rank descending, id ascending.  Needs n < 2^24.
+constexpr int32_t kMaxSampledN = (1 << 24) - 1;
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+// Threads of a union work-group and the largest hash table (entries) that fits
+// the LDS budget of one work-group.
+constexpr int kUnionThreads = 256;
+constexpr int kMaxHashLog2 = 14;  // 16384 entries = 64 KiB
+
+// Largest integer M the sampled path accepts: the per-vertex LDS hash table
+// holds 2 (M + 1 + kUnionThreads) entries.
+constexpr int32_t kMaxM = (1 << (kMaxHashLog2 - 1)) - 1 - kUnionThreads;
+
+// Per-run device state for the bulk peeling rounds (one instance in device memory).
+struct RoundState {
+    long long c;             // running maximum (core value of this round), starts at -1
+    long long min_key;       // reduction: min key over alive vertices
+    long long sum_val;       // reduction: sum of values over alive vertices
+    int alive_count;         // reduction: alive vertices at round start
+    int rcount;              // |R| of this round
+    int rounds;              // rounds that removed at least one vertex
+    int ncand;               // densest-core candidates recorded so far
+    int stop;                // early-stop decision of this round
+    int qcount;              // expansion chunk-queue fill
+    int front_lo, front_hi;  // current frontier range inside the affected list
+    int aff_fill;            // affected-list fill
+    int wl_count;            // union worklist fill
+    int changed_count[2];    // vertices whose (k, B) changed (ping-pong by level parity)
+    int overflow;            // an estimate exceeded the representable range
+    int pad;
+    unsigned long long te;     // edges traversed (exact h-degree work)
+    unsigned long long arcs;   // adjacency entries read by the h-degree kernels
+    unsigned long long elems;  // sample-list entries read by the union kernels
+};
+
+// ---- kernels: graph, ranks, bookkeeping (kh_graph.hip) -------------------------------
+
+void launch_ranks(uint8_t* r, int32_t n, uint64_t seed, uint32_t stream_id, hipStream_t s);
+void launch_validate(const int32_t* rp, const int32_t* col, int32_t n, int64_t nnz, int* err, hipStream_t s);
+void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s);
+void launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
+void launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t s);
+void launch_alive_from(const uint8_t* src, uint8_t* alive, int32_t n, hipStream_t s);
+void launch_alive_degree(const int32_t* rp, const int32_t* col, const uint8_t* alive, int32_t* adeg, int32_t n,
+                         hipStream_t s);
+void launch_compact_alive(const uint8_t* alive, int32_t n, int32_t* out, int* count, hipStream_t s);
+void launch_round_reset(RoundState* st, hipStream_t s);
+void launch_reduce(const int64_t* key, const int64_t* val, const uint8_t* alive, int32_t n, RoundState* st,
+                   hipStream_t s);
+void launch_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_size, int64_t* cand_sum, int early_stop,
+                        hipStream_t s);
+void launch_select(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core, int32_t* rlist,
+                   int32_t* mark, int32_t epoch, int kill, hipStream_t s);
+void launch_kill_list(const int32_t* list, const int* count, uint8_t* alive, hipStream_t s);
+// Chunk queue over the adjacency of list[*lo .. *hi) (lo/hi may be NULL: 0 and count).
+void launch_enqueue(const int32_t* list, const int* lo, const int* hi, const int32_t* rp, int32_t* qv, int32_t* qb,
+                    int* qcount, hipStream_t s);
+// mode 0: mark alive unmarked neighbours with `epoch` and append them to out[*out_count++]
+// mode 1: decrement adeg of alive neighbours
+void launch_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
+                   const uint8_t* alive, int32_t* mark, int32_t epoch, int mode, int32_t* out, int* out_count,
+                   int32_t* adeg, hipStream_t s);
+// front_lo = front_hi; front_hi = aff_fill; qcount = 0
+void launch_next_frontier(RoundState* st, hipStream_t s);
+// qcount = 0, wl_count = 0, changed_count[level & 1] = 0
+void launch_level_reset(RoundState* st, int level, hipStream_t s);
+void launch_set_int(int* p, int v, hipStream_t s);
+void launch_scan_i64(const int64_t* in, int64_t* out, int32_t n, int64_t* partials, hipStream_t s);
+void launch_core_to_i32(const int64_t* core, int32_t* out, int32_t n, int* overflow, hipStream_t s);
+
+// ---- kernels: bit-parallel multi-source bounded BFS (kh_msbfs.hip) ---------------------
+
+struct MsPlanes {
+    int Q;                // 64-bit words per vertex (sources per batch = 64 Q)
+    uint64_t* vis;        // n*Q, visited sets; kept all-zero between batches
+    uint64_t* frA;        // n*Q, frontier (ping)
+    uint64_t* frB;        // n*Q, frontier (pong)
+    uint64_t* acc;        // n*Q, OR accumulator for split / pushed vertices; kept all-zero
+    uint32_t* bmA;        // ceil(n/32), bit per vertex: frontier word nonzero (ping)
+    uint32_t* bmB;        // (pong)
+    uint32_t* bmT;        // touched-by-push bitmap
+    int32_t* touched;     // n, vertices touched by the push hop
+    int* touched_count;   // device counter
+    uint32_t* cnt;        // 64 Q per-source counters
+    uint64_t* valid;      // Q words: bits of the batch's sources
+};
+
+struct MsItems {
+    int32_t nitems;
+    int32_t* u;       // item vertex
+    int32_t* beg;     // first arc
+    int32_t* end;     // one past last arc
+    uint8_t* split;   // 1 if the vertex has several items
+    int32_t nsplit;
+    int32_t* split_list;  // vertices with several items
+};
+
+// One batch of ns <= 64 Q sources: deg[src[j]] = |N(src[j]; h, X)| - 1.
+void ms_batch(const MsPlanes& P, const MsItems& I, int32_t n, const int32_t* rp, const int32_t* col,
+              const uint8_t* alive, const int32_t* adeg, const int32_t* src, int ns, int h, int64_t* deg,
+              RoundState* st, hipStream_t s);
+
+// ---- kernels: sampled lists (kh_union.hip) ---------------------------------------------
+
+void launch_cap_level1(const int32_t* rp, int32_t n, int32_t M, int64_t* cap, hipStream_t s);
+void launch_cap_next(const int32_t* rp, const int32_t* col, int32_t n, int32_t M, const int64_t* cap_prev,
+                     int64_t* cap, hipStream_t s);
+// Level 1 (neighbour lists are singletons).  worklist == NULL: all vertices.
+void launch_union1(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
+                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int64_t* off, uint32_t* keys,
+                   int32_t* size, uint8_t* kk, int32_t* changed, int* changed_count, RoundState* st, hipStream_t s);
+// Level i >= 2.
+void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
+                  const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, const int64_t* off_prev,
+                  const uint32_t* keys_prev, const int32_t* size_prev, const uint8_t* k_prev, const int64_t* off,
+                  uint32_t* keys, int32_t* size, uint8_t* kk, int32_t* cursor, int32_t* changed, int* changed_count,
+                  RoundState* st, hipStream_t s);
+// Alg. 1 estimate from level h.  worklist == NULL: all vertices.
+void launch_estimate(const int32_t* worklist, const int* wl_count, int32_t n, const uint8_t* alive,
+                     const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, int64_t* d,
+                     RoundState* st, hipStream_t s);
+
+}  // namespace kh

@@ -1,0 +1,186 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Every comparison is element by element and bit-exact: the whole path is
+integer arithmetic and its results do not depend on the deletion order.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+kh = pytest.importorskip("paper_2112_06154_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = kh.Context(0)
+    yield c
+    c.close()
+
+
+def graphs_small():
+    return [
+        gg.workload("er2k"),
+        gg.barabasi_albert(1500, 3, seed=4),
+        gg.chung_lu(1000, 3500, 2.1, seed=5),
+        gg.disjoint_union(gg.erdos_renyi(300, 700, seed=6), gg.path(40), gg.empty(7), gg.clique(30), gg.star(200)),
+    ]
+
+
+def test_ranks_bit_identical(ctx):
+    n = 1_000_000
+    for seed, sid in ((0, 0), (12345, 0), (12345, 1), (2 ** 63 + 17, 1)):
+        say("ranks", seed, sid)
+        got = kh.ranks(ctx, n, seed, sid).cpu().numpy()
+        assert np.array_equal(got, oracle.ranks(n, seed, sid))
+
+
+@pytest.mark.parametrize("gi", range(4))
+def test_hdeg_matches_oracle(ctx, gi):
+    g = graphs_small()[gi]
+    G = kh.Graph.from_gg(ctx, g)
+    rng = np.random.default_rng(gi)
+    for h in (1, 2, 3, 4):
+        for use_alive in (False, True):
+            say("hdeg", g.name, h, use_alive)
+            alive = None
+            alive_np = None
+            if use_alive:
+                alive_np = (rng.random(g.n) < 0.7).astype(np.uint8)
+                alive = torch.from_numpy(alive_np).cuda()
+            got, te = kh.hdeg(G, h, alive)
+            want, te_want = oracle.hdeg(g, h, alive_np, with_te=True)
+            assert np.array_equal(got.astype(np.int64), want)
+            assert te == te_want
+
+
+def test_hdeg_hub_and_ragged(ctx):
+    # a hub split across many work items, long paths, isolated vertices
+    g = gg.disjoint_union(gg.star(20000), gg.path(3001), gg.empty(33), gg.clique(70))
+    G = kh.Graph.from_gg(ctx, g)
+    for h in (1, 2, 3):
+        say("hdeg hub", h)
+        got, te = kh.hdeg(G, h)
+        want, te_want = oracle.hdeg(g, h, with_te=True)
+        assert np.array_equal(got.astype(np.int64), want)
+        assert te == te_want
+
+
+@pytest.mark.parametrize("gi", range(4))
+def test_exact_core_matches_oracle(ctx, gi):
+    g = graphs_small()[gi]
+    G = kh.Graph.from_gg(ctx, g)
+    for h in (1, 2, 3):
+        say("exact", g.name, h)
+        got, res = kh.core(G, h)
+        want, te = oracle.exact_core(g, h, with_te=True)
+        assert np.array_equal(got.astype(np.int64), want)
+        assert res["max_core"] == int(want.max())
+
+
+def test_exact_edge_cases(ctx):
+    for g, h, expect in [
+        (gg.empty(1), 2, [0]),
+        (gg.empty(5), 3, [0] * 5),
+        (gg.path(2), 2, [1, 1]),
+        (gg.path(9), 2, [2] * 9),
+        (gg.cycle(11), 2, [4] * 11),
+        (gg.clique(40), 3, [39] * 40),
+        (gg.star(100000), 2, [100000] * 100001),
+        (gg.star(100000), 1, [1] * 100001),
+    ]:
+        say("exact edge", g.name, h)
+        G = kh.Graph.from_gg(ctx, g)
+        got, _ = kh.core(G, h)
+        assert got.tolist() == expect
+    # n = 0
+    G = kh.Graph(ctx, 0, np.zeros(1, np.int32), np.zeros(0, np.int32))
+    got, _ = kh.core(G, 2)
+    assert got.size == 0
+
+
+@pytest.mark.parametrize("gi", range(4))
+def test_sampled_lists_match_closed_form(ctx, gi):
+    g = graphs_small()[gi]
+    G = kh.Graph.from_gg(ctx, g)
+    rng = np.random.default_rng(10 + gi)
+    for M in (7, 40):
+        for use_alive in (False, True):
+            alive_np = (rng.random(g.n) < 0.8).astype(np.uint8) if use_alive else None
+            alive = torch.from_numpy(alive_np).cuda() if use_alive else None
+            r = oracle.ranks(g.n, 99)
+            for level in (1, 2, 3):
+                say("lists", g.name, M, use_alive, level)
+                k, sz, mem, est = kh.sampled_lists(G, 3, level, epsilon=0.5, seed=99, M_override=M, alive=alive)
+                ko, so, offo, memo = oracle.sampled_lists(g, level, r, M, alive_np)
+                assert np.array_equal(k, ko)
+                assert np.array_equal(sz, so)
+                for v in range(g.n):
+                    assert np.array_equal(mem[v], memo[offo[v]:offo[v + 1]]), v
+            want_est = oracle.estimate_all(g, 3, r, M, alive_np)
+            assert np.array_equal(est, want_est)
+
+
+@pytest.mark.parametrize("gi", range(4))
+def test_sampled_core_matches_oracle(ctx, gi):
+    g = graphs_small()[gi]
+    G = kh.Graph.from_gg(ctx, g)
+    for h in (2, 3):
+        for M in (5, 30, 0):
+            seed = 1000 + gi
+            Mi = M if M else oracle.M_int(g.n, 0.5)
+            say("sampled", g.name, h, Mi)
+            got, res = kh.core(G, h, epsilon=0.5, seed=seed, M_override=M)
+            want = oracle.sampled_core(g, h, oracle.ranks(g.n, seed), Mi)
+            assert res["M_used"] == Mi
+            assert np.array_equal(got.astype(np.int64), want)
+
+
+def test_sampled_with_M_ge_n_is_exact(ctx):
+    g = gg.barabasi_albert(800, 3, seed=8)
+    G = kh.Graph.from_gg(ctx, g)
+    for h in (2, 3):
+        say("sampled M>=n", h)
+        got, _ = kh.core(G, h, epsilon=0.5, seed=3, M_override=g.n)
+        ex, _ = kh.core(G, h)
+        assert np.array_equal(got, ex)
+        assert np.array_equal(got.astype(np.int64), oracle.exact_core(g, h))
+
+
+def test_dense_exact_matches_oracle(ctx):
+    for g in graphs_small()[:2]:
+        G = kh.Graph.from_gg(ctx, g)
+        for h in (2, 3):
+            for prune in (False, True):
+                say("dense exact", g.name, h, prune)
+                got, res = kh.core(G, h, dense=True, prune=prune)
+                want = oracle.dense(g, got, h, "exact", prune=prune, eps=0.0)
+                assert (res["dense_k"], res["dense_size"], res["dense_R"]) == (want["k"], want["size"], want["R"])
+                res2 = kh.dense(G, got, h, prune=prune)
+                assert (res2["dense_k"], res2["dense_size"], res2["dense_R"]) == (want["k"], want["size"], want["R"])
+
+
+def test_dense_sampled_matches_oracle(ctx):
+    for g in graphs_small()[:2]:
+        G = kh.Graph.from_gg(ctx, g)
+        for h in (2, 3):
+            for prune in (False, True):
+                say("dense sampled", g.name, h, prune)
+                got, res = kh.core(G, h, epsilon=0.5, seed=21, M_override=25, M_dense_override=40, dense=True,
+                                   prune=prune)
+                want = oracle.dense(g, got, h, "sampled", oracle.ranks(g.n, 21, 1), 40, prune=prune, eps=0.5)
+                assert res["M_dense_used"] == 40
+                assert (res["dense_k"], res["dense_size"], res["dense_R"]) == (want["k"], want["size"], want["R"])
