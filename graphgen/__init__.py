@@ -113,16 +113,16 @@ def from_edges(n: int, edges, name: str = "") -> Graph:
     if e.size and (e.min() < 0 or e.max() >= n):
         raise ValueError("edge endpoint out of range")
     e = e[e[:, 0] != e[:, 1]]
+    nn = np.int64(max(n, 1))
     lo = np.minimum(e[:, 0], e[:, 1])
     hi = np.maximum(e[:, 0], e[:, 1])
-    keys = np.unique(lo * np.int64(max(n, 1)) + hi)
-    lo = keys // max(n, 1)
-    hi = keys % max(n, 1)
-    src = np.concatenate([lo, hi])
-    dst = np.concatenate([hi, lo])
-    order = np.lexsort((dst, src))
-    src = src[order]
-    dst = dst[order]
+    keys = np.unique(lo * nn + hi)
+    lo = keys // nn
+    hi = keys % nn
+    arc = np.concatenate([lo * nn + hi, hi * nn + lo])
+    arc.sort()
+    src = arc // nn
+    dst = arc % nn
     deg = np.bincount(src, minlength=n) if n > 0 else np.zeros(0, np.int64)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(deg, out=row_ptr[1:])
@@ -175,10 +175,9 @@ def erdos_renyi(n: int, m: int, seed: int = 1, permute: bool = True) -> Graph:
         return _uniform_below(x[0::2], n), _uniform_below(x[1::2], n)
 
     e = _first_distinct_pairs(n, m, draw, "er")
-    g = from_edges(n, e, f"er_n{n}_m{m}_s{seed}")
     if permute:
-        g = relabel(g, random_permutation(n, seed))
-    return g
+        e = random_permutation(n, seed)[e]
+    return from_edges(n, e, f"er_n{n}_m{m}_s{seed}")
 
 
 def chung_lu(n: int, m: int, gamma: float, seed: int = 1, permute: bool = True) -> Graph:
@@ -196,10 +195,9 @@ def chung_lu(n: int, m: int, gamma: float, seed: int = 1, permute: bool = True) 
         return np.minimum(a, n - 1).astype(np.int64), np.minimum(b, n - 1).astype(np.int64)
 
     e = _first_distinct_pairs(n, m, draw, "cl")
-    g = from_edges(n, e, f"cl_n{n}_m{m}_g{gamma}_s{seed}")
     if permute:
-        g = relabel(g, random_permutation(n, seed))
-    return g
+        e = random_permutation(n, seed)[e]
+    return from_edges(n, e, f"cl_n{n}_m{m}_g{gamma}_s{seed}")
 
 
 def barabasi_albert(n: int, k: int = 3, seed: int = 1, permute: bool = True) -> Graph:
@@ -234,10 +232,10 @@ def barabasi_albert(n: int, k: int = 3, seed: int = 1, permute: bool = True) -> 
             ends[ne] = c
             ends[ne + 1] = t
             ne += 2
-    g = from_edges(n, edges, f"ba_n{n}_k{k}_s{seed}")
+    e = np.asarray(edges, dtype=np.int64)
     if permute:
-        g = relabel(g, random_permutation(n, seed))
-    return g
+        e = random_permutation(n, seed)[e]
+    return from_edges(n, e, f"ba_n{n}_k{k}_s{seed}")
 
 
 # ---- small deterministic shapes ---------------------------------------------

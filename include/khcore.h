@@ -168,6 +168,21 @@ kh_status kh_sampled_lists(kh_graph *g, const kh_params *params, const uint8_t *
  * KH_DENSE_PRUNE restricts K as in kh_params. */
 kh_status kh_dense(kh_graph *g, const kh_params *params, const int32_t *core_in, kh_result *res, void *stream);
 
+/* ---- measurement hooks ------------------------------------------------------ */
+
+/* Start (on != 0; resets the totals) or stop recording the h-degree pull
+ * kernel: every launch is bracketed by HIP events on the stream it runs on,
+ * and the kernel counts the bytes it must move (work items, adjacency ids,
+ * visited/frontier words read and written) and, separately, the neighbour
+ * frontier words it gathers. */
+kh_status kh_profile_enable(kh_context *ctx, int32_t on);
+
+/* Totals since kh_profile_enable(ctx, 1): launches, summed kernel time (ms),
+ * algorithmic bytes without gathers, and gathered bytes.  Any pointer may be
+ * NULL.  Synchronises the recorded events. */
+kh_status kh_profile_read(kh_context *ctx, int64_t *launches, double *total_ms, int64_t *alg_bytes,
+                          int64_t *gather_bytes);
+
 #ifdef __cplusplus
 }
 #endif

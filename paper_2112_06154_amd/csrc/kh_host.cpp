@@ -21,6 +21,8 @@
 #include <chrono>
 #include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -62,6 +64,12 @@ struct kh_context {
     size_t lds_per_block = 65536;
     int num_cu = 0;
     RoundState* host_state = nullptr;  // pinned mirror of the device round state
+    // pull-kernel timing (kh_profile_enable / kh_profile_read)
+    bool prof_on = false;
+    PullTimer timer;
+    long long prof_launches = 0;
+    double prof_ms = 0.0;
+    unsigned long long prof_bytes = 0, prof_gather = 0;
 };
 
 namespace {
@@ -219,7 +227,75 @@ extern "C" kh_status kh_context_create(int32_t device, uint64_t hbm_budget_bytes
 extern "C" void kh_context_destroy(kh_context* ctx) {
     if (!ctx) return;
     if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+    if (ctx->timer.ev) {
+        for (int i = 0; i < 2 * ctx->timer.cap; ++i) (void)hipEventDestroy(ctx->timer.ev[i]);
+        delete[] ctx->timer.ev;
+    }
     delete ctx;
+}
+
+namespace {
+
+// Fold the recorded pull launches into the context totals.
+void prof_collect(kh_context* ctx) {
+    PullTimer& T = ctx->timer;
+    for (int i = 0; i < T.used; ++i) {
+        float ms = 0.f;
+        hip_ok(hipEventSynchronize(T.ev[2 * i + 1]));
+        hip_ok(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
+        ctx->prof_ms += ms;
+        ctx->prof_launches += 1;
+    }
+    T.used = 0;
+}
+
+void prof_add_counters(kh_context* ctx, const RoundState& hs) {
+    if (!ctx->prof_on) return;
+    prof_collect(ctx);
+    ctx->prof_bytes += hs.pull_bytes;
+    ctx->prof_gather += hs.pull_gather;
+}
+
+}  // namespace
+
+extern "C" kh_status kh_profile_enable(kh_context* ctx, int32_t on) {
+    if (!ctx) return KH_EINVAL;
+    try {
+        hip_ok(hipSetDevice(ctx->device));
+        if (on && !ctx->timer.ev) {
+            const int cap = 8192;
+            ctx->timer.ev = new hipEvent_t[2 * cap];
+            for (int i = 0; i < 2 * cap; ++i) hip_ok(hipEventCreate(&ctx->timer.ev[i]));
+            ctx->timer.cap = cap;
+        }
+        if (ctx->prof_on) prof_collect(ctx);
+        ctx->timer.used = 0;
+        ctx->prof_on = on != 0;
+        if (on) {
+            ctx->prof_launches = 0;
+            ctx->prof_ms = 0.0;
+            ctx->prof_bytes = 0;
+            ctx->prof_gather = 0;
+        }
+    } catch (const KhError& e) {
+        return e.code;
+    }
+    return KH_OK;
+}
+
+extern "C" kh_status kh_profile_read(kh_context* ctx, int64_t* launches, double* total_ms, int64_t* alg_bytes,
+                                     int64_t* gather_bytes) {
+    if (!ctx) return KH_EINVAL;
+    try {
+        if (ctx->prof_on) prof_collect(ctx);
+    } catch (const KhError& e) {
+        return e.code;
+    }
+    if (launches) *launches = ctx->prof_launches;
+    if (total_ms) *total_ms = ctx->prof_ms;
+    if (alg_bytes) *alg_bytes = (int64_t)ctx->prof_bytes;
+    if (gather_bytes) *gather_bytes = (int64_t)ctx->prof_gather;
+    return KH_OK;
 }
 
 namespace {
@@ -331,6 +407,15 @@ extern "C" int64_t kh_graph_nnz(const kh_graph* g) { return g ? g->nnz : -1; }
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+// Opt-in progress trace on stderr (KH_TRACE=1): one line per traced round.
+bool trace_on() {
+    static const bool on = [] {
+        const char* e = std::getenv("KH_TRACE");
+        return e && e[0] && e[0] != '0';
+    }();
+    return on;
+}
 
 void check_params(const kh_graph* g, const kh_params* P) {
     if (!g || !P) fail(KH_EINVAL);
@@ -447,9 +532,11 @@ struct Planes {
         hip_ok(hipMemsetAsync(acc.p, 0, acc.count * 8, s));
         hip_ok(hipMemsetAsync(cnt.p, 0, cnt.count * 4, s));
     }
+    PullTimer* timer = nullptr;
     MsPlanes view(int q) const {
         MsPlanes P;
         P.Q = q;
+        P.timer = timer;
         P.vis = vis.p;
         P.frA = frA.p;
         P.frB = frB.p;
@@ -469,7 +556,10 @@ struct Planes {
 void hdeg_sources(kh_graph* g, Planes& PL, const uint8_t* alive, const int32_t* adeg, const int32_t* src, int64_t count,
                   int h, int64_t* deg, RoundState* st, hipStream_t s) {
     int64_t done = 0;
+    kh_context* ctx = g->ctx;
+    PL.timer = ctx->prof_on ? &ctx->timer : nullptr;
     while (done < count) {
+        if (PL.timer && PL.timer->used + 8 >= PL.timer->cap) prof_collect(ctx);
         const int64_t rest = count - done;
         const int q = std::min(PL.qmax, pick_q(rest));
         const int ns = (int)std::min<int64_t>(rest, 64ll * q);
@@ -547,6 +637,7 @@ struct ExactRun {
     RoundState fin{};
 
     void run(const uint8_t* alive_in, const int64_t* key_ext) {
+        const auto t_begin = Clock::now();
         kh_context* ctx = g->ctx;
         const int32_t n = g->n;
         build_items(g, s);
@@ -580,6 +671,10 @@ struct ExactRun {
         hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, ctx->host_state->aff_fill, h, deg.p, st.p, s);
         const int64_t* key = key_ext ? key_ext : deg.p;
         int32_t epoch = 0;
+        const auto t_start = Clock::now();
+        if (trace_on())
+            std::fprintf(stderr, "[kh exact] n %d h %d initial degrees %.3fs\n", n, h,
+                         std::chrono::duration<double>(Clock::now() - t_begin).count());
         for (;;) {
             ++epoch;
             launch_round_reset(st.p, s);
@@ -606,9 +701,14 @@ struct ExactRun {
             if (hs.alive_count == 0) break;
             // every round deletes at least the minimum vertex
             if (hs.rounds > n + 1) fail(KH_EDEVICE);
+            if (trace_on() && (hs.rounds < 8 || (hs.rounds & 63) == 0))
+                std::fprintf(stderr, "[kh exact] round %d c %lld alive %d removed %d affected %d t %.3fs\n", hs.rounds,
+                             hs.c, hs.alive_count, hs.rcount, hs.aff_fill,
+                             std::chrono::duration<double>(Clock::now() - t_start).count());
             if (hs.aff_fill > 0) hdeg_sources(g, PL, alive.p, adeg.p, alist.p, hs.aff_fill, h, deg.p, st.p, s);
         }
         fin = *ctx->host_state;
+        prof_add_counters(ctx, fin);
         cands = read_candidates(fin, ck, cs, cr, s);
     }
 };
@@ -738,6 +838,7 @@ struct SampledRun {
         int32_t* changed[2] = {chA.p, chB.p};
         int32_t epoch = 0;
         const int batch = 8;
+        const auto t_start = Clock::now();
         for (;;) {
             for (int r = 0; r < batch; ++r) {
                 launch_round_reset(st.p, s);
@@ -770,6 +871,11 @@ struct SampledRun {
             if (ctx->host_state->alive_count == 0) break;
             // every round deletes at least the minimum vertex
             if (ctx->host_state->rounds > n + 1) fail(KH_EDEVICE);
+            if (trace_on() && ((ctx->host_state->rounds & 255) < batch))
+                std::fprintf(stderr, "[kh sampled] round %d c %lld alive %d removed %d worklist %d t %.3fs\n",
+                             ctx->host_state->rounds, ctx->host_state->c, ctx->host_state->alive_count,
+                             ctx->host_state->rcount, ctx->host_state->wl_count,
+                             std::chrono::duration<double>(Clock::now() - t_start).count());
         }
         fin = *ctx->host_state;
         cands = read_candidates(fin, ck, cs, cr, s);
@@ -971,6 +1077,7 @@ extern "C" kh_status kh_hdeg(kh_graph* g, int32_t h, const uint8_t* alive_in, ui
         finish_core(ctx, deg.p, n, deg_out, (flags & KH_OUT_DEVICE) != 0, s, nullptr);
         read_state(ctx, st.p, s);
         if (edges_traversed) *edges_traversed = (int64_t)ctx->host_state->te;
+        prof_add_counters(ctx, *ctx->host_state);
     } catch (const KhError& e) {
         return e.code;
     } catch (const std::bad_alloc&) {

@@ -48,6 +48,16 @@ struct RoundState {
     unsigned long long te;     // edges traversed (exact h-degree work)
     unsigned long long arcs;   // adjacency entries read by the h-degree kernels
     unsigned long long elems;  // sample-list entries read by the union kernels
+    unsigned long long pull_bytes;   // algorithmic bytes of the pull kernel (without neighbour gathers)
+    unsigned long long pull_gather;  // bytes of neighbour frontier words gathered by the pull kernel
+};
+
+// Optional HIP-event timing of every launch of the h-degree pull kernel, on the
+// stream it is launched on.
+struct PullTimer {
+    hipEvent_t* ev = nullptr;  // pairs: ev[2i] before, ev[2i+1] after launch i
+    int cap = 0;
+    int used = 0;
 };
 
 // ---- kernels: graph, ranks, bookkeeping (kh_graph.hip) -------------------------------
@@ -101,6 +111,7 @@ struct MsPlanes {
     int* touched_count;   // device counter
     uint32_t* cnt;        // 64 Q per-source counters
     uint64_t* valid;      // Q words: bits of the batch's sources
+    PullTimer* timer;     // nullable
 };
 
 struct MsItems {

@@ -127,10 +127,12 @@ __global__ __launch_bounds__(256) void k_ms_pull(int32_t nitems, const int32_t* 
     const int gpb = blockDim.x / Q;
     const int ngroups = gridDim.x * gpb;
     const uint64_t vm = valid[j];
-    unsigned long long te = 0, arcs = 0;
+    unsigned long long te = 0, arcs = 0, bytes = 0, gath = 0;
     for (int it = blockIdx.x * gpb + threadIdx.x / Q; it < nitems; it += ngroups) {
         const int32_t u = item_u[it];
+        if (j == 0) bytes += 14;  // item (u, beg, end, split) and alive[u]
         if (!alive[u]) continue;
+        if (j == 0) bytes += 8 * Q;  // vis[u]
         const size_t at = (size_t)u * Q + j;
         const uint64_t vw = vis[at];
         const bool full = (vw & vm) == vm;
@@ -140,22 +142,30 @@ __global__ __launch_bounds__(256) void k_ms_pull(int32_t nitems, const int32_t* 
         int32_t p = b;
         while (p < e) {
             const int32_t w = col[p];
-            if ((bm_cur[w >> 5] >> (w & 31)) & 1u) a |= fr_cur[(size_t)w * Q + j];
+            if ((bm_cur[w >> 5] >> (w & 31)) & 1u) {
+                a |= fr_cur[(size_t)w * Q + j];
+                if (j == 0) gath += 8 * Q;
+            }
             ++p;
             if (((p - b) & 15) == 0) {
                 const bool f = ((a | vw) & vm) == vm;
                 if ((__ballot(f) & gmask) == gmask) break;
             }
         }
-        if (j == 0) arcs += (unsigned long long)(p - b);
+        if (j == 0) {
+            arcs += (unsigned long long)(p - b);
+            bytes += 4ull * (unsigned long long)(p - b);  // col[]
+        }
         if (item_split[it]) {
             const uint64_t nw = a & ~vw & vm;
             if (nw) atomicOr((unsigned long long*)&acc[at], (unsigned long long)nw);
+            if ((__ballot(nw != 0ull) & gmask) != 0ull && j == 0) bytes += 8 * Q;
         } else {
             const uint64_t nw = a & ~vw & vm;
             const bool any = (__ballot(nw != 0ull) & gmask) != 0ull;
             if (any) {
                 if (nw) vis[at] = vw | nw;
+                if (j == 0) bytes += (last ? 8 : 16) * Q;  // vis (+ next frontier) write
                 if (!last) {
                     fr_next[at] = nw;
                     if (j == 0) atomicOr(&bm_next[u >> 5], 1u << (u & 31));
@@ -166,9 +176,13 @@ __global__ __launch_bounds__(256) void k_ms_pull(int32_t nitems, const int32_t* 
     }
     te = (unsigned long long)wave_sum_ll((long long)te);
     arcs = (unsigned long long)wave_sum_ll((long long)arcs);
+    bytes = (unsigned long long)wave_sum_ll((long long)bytes);
+    gath = (unsigned long long)wave_sum_ll((long long)gath);
     if (l == 0) {
         if (te) atomicAdd(&st->te, te);
         if (arcs) atomicAdd(&st->arcs, arcs);
+        if (bytes) atomicAdd(&st->pull_bytes, bytes);
+        if (gath) atomicAdd(&st->pull_gather, gath);
     }
 }
 
@@ -245,8 +259,15 @@ static void ms_batch_q(const MsPlanes& P, const MsItems& I, int32_t n, const int
         const int last = t == h ? 1 : 0;
         if (!last) launch_fill_u32(bm_nxt, 0u, bmwords, s);
         const int pull_grid = grid_for((int64_t)I.nitems * Q, 256, 16384);
+        PullTimer* T = P.timer;
+        const bool timed = T && T->used < T->cap;
+        if (timed) (void)hipEventRecord(T->ev[2 * T->used], s);
         hipLaunchKernelGGL(k_ms_pull<Q>, dim3(pull_grid), dim3(256), 0, s, I.nitems, I.u, I.beg, I.end, I.split, col,
                            alive, P.vis, fr_cur, bm_cur, fr_nxt, bm_nxt, P.acc, P.valid, last, adeg, st);
+        if (timed) {
+            (void)hipEventRecord(T->ev[2 * T->used + 1], s);
+            T->used += 1;
+        }
         if (I.nsplit > 0)
             hipLaunchKernelGGL(k_ms_finalize<Q>, dim3(grid_for((int64_t)I.nsplit * Q, 256, 4096)), dim3(256), 0, s,
                                I.split_list, (const int*)nullptr, I.nsplit, P.acc, P.vis, fr_nxt, bm_nxt, P.valid,

@@ -38,7 +38,7 @@ KH_OUT_DEVICE = 8
 EXPORTED = [
     "kh_status_str", "kh_buffer_size", "kh_validate_csr", "kh_context_create", "kh_context_destroy",
     "kh_graph_load_csr", "kh_graph_free", "kh_graph_n", "kh_graph_nnz", "kh_core", "kh_hdeg", "kh_ranks",
-    "kh_sampled_lists", "kh_dense",
+    "kh_sampled_lists", "kh_dense", "kh_profile_enable", "kh_profile_read",
 ]
 
 
@@ -104,6 +104,11 @@ def lib():
         L.kh_sampled_lists.restype = i32
         L.kh_dense.argtypes = [P, ctypes.POINTER(Params), P, ctypes.POINTER(Result), P]
         L.kh_dense.restype = i32
+        L.kh_profile_enable.argtypes = [P, i32]
+        L.kh_profile_enable.restype = i32
+        L.kh_profile_read.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64)]
+        L.kh_profile_read.restype = i32
         _lib = L
     return _lib
 
@@ -161,6 +166,17 @@ class Context:
         if self.handle:
             lib().kh_context_destroy(self.handle)
             self.handle = None
+
+    def profile(self, on: bool) -> None:
+        """Start (resetting totals) or stop HIP-event timing of the h-degree pull kernel."""
+        _check(lib().kh_profile_enable(self.handle, int(on)), "kh_profile_enable")
+
+    def profile_read(self) -> dict:
+        la, by, ga = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(lib().kh_profile_read(self.handle, ctypes.byref(la), ctypes.byref(ms), ctypes.byref(by),
+                                     ctypes.byref(ga)), "kh_profile_read")
+        return {"launches": la.value, "ms": ms.value, "alg_bytes": by.value, "gather_bytes": ga.value}
 
     def __del__(self):
         try:
