@@ -172,6 +172,8 @@ __global__ void k_round_reset(RoundState* st) {
     st->wl_count = 0;
     st->changed_count[0] = 0;
     st->changed_count[1] = 0;
+    st->rc_count = 0;
+    st->opt_count = 0;
 }
 void launch_round_reset(RoundState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, s, st);
@@ -350,6 +352,7 @@ void launch_next_frontier(RoundState* st, hipStream_t s) {
 __global__ void k_level_reset(RoundState* st, int level) {
     st->qcount = 0;
     st->wl_count = 0;
+    st->rc_count = 0;
     st->changed_count[level & 1] = 0;
 }
 void launch_level_reset(RoundState* st, int level, hipStream_t s) {
@@ -450,6 +453,163 @@ __global__ void k_core_to_i32(const int64_t* __restrict__ core, int32_t* __restr
 void launch_core_to_i32(const int64_t* core, int32_t* out, int32_t n, int* overflow, hipStream_t s) {
     if (n > 0)
         hipLaunchKernelGGL(k_core_to_i32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, core, out, n, overflow);
+}
+
+// ---- lower bounds for the lazy exact peel ---------------------------------------------------
+// For h >= 2 and any alive x within distance h-1 of v in G[X],
+// N(x;1,X) is contained in N(v;h,X), so |A(x) ∩ X| <= deg_h(v;X).  The anchor
+// chain v, anchor(v), anchor(anchor(v)), ... walks alive edges, so every vertex
+// on its first h-1 steps qualifies.
+__global__ void k_anchor(const int32_t* __restrict__ list, const int* count, int32_t n, const int32_t* __restrict__ rp,
+                         const int32_t* __restrict__ col, const uint8_t* __restrict__ alive,
+                         const int32_t* __restrict__ adeg, int32_t* __restrict__ anchor, int only_dead) {
+    const int total = list ? *count : n;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int l = lane_id();
+    for (int i = wave; i < total; i += nwaves) {
+        const int32_t v = list ? list[i] : i;
+        if (!alive[v]) continue;
+        if (only_dead) {
+            const int32_t a = anchor[v];
+            if (a >= 0 && alive[a]) continue;
+        }
+        long long best = -1;
+        for (int32_t p = rp[v] + l; p < rp[v + 1]; p += 64) {
+            const int32_t w = col[p];
+            if (alive[w]) {
+                const long long key = ((long long)adeg[w] << 32) | (long long)(0x7FFFFFFF - w);
+                best = key > best ? key : best;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const long long t = __shfl_xor(best, o);
+            best = t > best ? t : best;
+        }
+        if (l == 0) anchor[v] = best < 0 ? -1 : (int32_t)(0x7FFFFFFF - (int32_t)(best & 0x7FFFFFFF));
+    }
+}
+void launch_anchor(const int32_t* list, const int* count, int32_t n, const int32_t* rp, const int32_t* col,
+                   const uint8_t* alive, const int32_t* adeg, int32_t* anchor, int only_dead, hipStream_t s) {
+    if (n <= 0) return;
+    const int grid = list ? 2048 : grid_for((int64_t)n * 64, 256, 16384);
+    hipLaunchKernelGGL(k_anchor, dim3(grid), dim3(256), 0, s, list, count, n, rp, col, alive, adeg, anchor,
+                       only_dead);
+}
+
+__global__ void k_lower_bound(const int32_t* __restrict__ list, const int* count, int32_t n, int h,
+                              const uint8_t* __restrict__ alive, const int32_t* __restrict__ adeg,
+                              const int32_t* __restrict__ anchor, int64_t* __restrict__ deg,
+                              uint8_t* __restrict__ exact) {
+    const int total = list ? *count : n;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int32_t v = list ? list[i] : i;
+        if (!alive[v]) continue;
+        long long lb = adeg[v];
+        int32_t x = v;
+        for (int t = 1; t < h; ++t) {
+            x = anchor[x];
+            if (x < 0 || !alive[x]) break;
+            const long long a = adeg[x];
+            lb = a > lb ? a : lb;
+        }
+        deg[v] = lb;
+        exact[v] = h == 1 ? 1 : 0;
+    }
+}
+void launch_lower_bound(const int32_t* list, const int* count, int32_t n, int h, const uint8_t* alive,
+                        const int32_t* adeg, const int32_t* anchor, int64_t* deg, uint8_t* exact, hipStream_t s) {
+    if (n <= 0) return;
+    const int grid = list ? 1024 : grid_for(n, 256, 8192);
+    hipLaunchKernelGGL(k_lower_bound, dim3(grid), dim3(256), 0, s, list, count, n, h, alive, adeg, anchor, deg,
+                       exact);
+}
+
+__global__ void k_lazy_candidates(const uint8_t* __restrict__ alive, const int64_t* __restrict__ deg,
+                                  const uint8_t* __restrict__ exact, int32_t n, RoundState* st,
+                                  int32_t* __restrict__ out, int pass, int opt_cap) {
+    if (st->alive_count == 0) return;
+    const long long c = st->min_key > st->c ? st->min_key : st->c;
+    const long long hi = c + c / 8 + 32;
+    const int base_fill = pass ? st->rc_count : 0;
+    const int room = opt_cap - base_fill;
+    if (pass && room <= 0) return;
+    const int32_t stride = gridDim.x * blockDim.x;
+    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int32_t v = base + threadIdx.x;
+        bool want = false;
+        if (v < n && alive[v] && !exact[v]) {
+            const long long d = deg[v];
+            want = pass ? (d > c && d <= hi) : (d <= c);
+        }
+        if (!pass) {
+            const int slot = wave_append_slot(want, &st->rc_count);
+            if (want) out[slot] = v;
+        } else {
+            if (*(volatile int*)&st->opt_count >= room) continue;
+            const int slot = wave_append_slot(want, &st->opt_count);
+            if (want && slot < room) out[base_fill + slot] = v;
+        }
+    }
+}
+void launch_lazy_candidates(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
+                            int32_t* out, int pass, int opt_cap, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_lazy_candidates, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, alive, deg, exact, n, st,
+                           out, pass, opt_cap);
+}
+
+// Deleting R can only remove from N(v;h,X) vertices within distance h - t of R,
+// t = dist(v, R): a shortest path from v that needed R reaches some r in R after
+// at least t steps and has at most h - t left.  So
+//     deg_h(v; X \ R) >= deg_h(v; X) - |N(R; h - t, X)|,
+// and |N(R; s, X)| = |R| + (vertices the BFS from R found in hops 1..s).
+__global__ void k_decay_bound(const int32_t* __restrict__ alist, RoundState* st, const int* __restrict__ hopfill,
+                              int h, const uint8_t* __restrict__ alive, const int32_t* __restrict__ adeg,
+                              const int32_t* __restrict__ anchor, int64_t* __restrict__ deg,
+                              uint8_t* __restrict__ exact) {
+    const int total = st->aff_fill;
+    const long long rc = st->rcount;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int32_t v = alist[i];
+        if (!alive[v]) continue;
+        if (h == 1) {
+            deg[v] = adeg[v];
+            exact[v] = 1;
+            continue;
+        }
+        int t = 1;
+        while (t < h && i >= hopfill[t]) ++t;
+        const long long lost = rc + (h - t >= 1 ? (long long)hopfill[h - t] : 0ll);
+        long long lb = deg[v] - lost;
+        long long ab = adeg[v];
+        int32_t x = v;
+        for (int q = 1; q < h; ++q) {
+            x = anchor[x];
+            if (x < 0 || !alive[x]) break;
+            const long long a = adeg[x];
+            ab = a > ab ? a : ab;
+        }
+        deg[v] = lb > ab ? lb : ab;
+        exact[v] = 0;
+    }
+}
+void launch_decay_bound(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
+                        const int32_t* adeg, const int32_t* anchor, int64_t* deg, uint8_t* exact, hipStream_t s) {
+    hipLaunchKernelGGL(k_decay_bound, dim3(1024), dim3(256), 0, s, alist, st, hopfill, h, alive, adeg, anchor, deg,
+                       exact);
+}
+
+__global__ void k_record_fill(RoundState* st, int* hopfill, int t) { hopfill[t] = st->aff_fill; }
+void launch_record_fill(RoundState* st, int* hopfill, int t, hipStream_t s) {
+    hipLaunchKernelGGL(k_record_fill, dim3(1), dim3(1), 0, s, st, hopfill, t);
+}
+
+__global__ void k_set_flags(const int32_t* __restrict__ list, int count, uint8_t* __restrict__ flags, uint8_t v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) flags[list[i]] = v;
+}
+void launch_set_flags(const int32_t* list, int count, uint8_t* flags, uint8_t v, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_set_flags, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, list, count, flags, v);
 }
 
 }  // namespace kh

@@ -628,19 +628,17 @@ struct ExactRun {
     kh_graph* g;
     int h;
     hipStream_t s;
-    Buf<uint8_t> alive;
-    Buf<int32_t> adeg, mark, rlist, alist, qv, qb, srcl;
+    Buf<uint8_t> alive, exact;
+    Buf<int32_t> adeg, mark, rlist, alist, qv, qb, srcl, anchor, hopfill;
     Buf<int64_t> deg, core, ck, cs, cr;
     Buf<RoundState> st;
     Planes PL;
     Candidates cands;
     RoundState fin{};
+    long long recomputed = 0;  // exact h-degree evaluations
 
-    void run(const uint8_t* alive_in, const int64_t* key_ext) {
-        const auto t_begin = Clock::now();
+    void alloc(int32_t n) {
         kh_context* ctx = g->ctx;
-        const int32_t n = g->n;
-        build_items(g, s);
         alive.alloc(ctx, n);
         adeg.alloc(ctx, n);
         mark.alloc(ctx, n);
@@ -659,52 +657,130 @@ struct ExactRun {
         PL.alloc(ctx, n, pick_q(n));
         PL.clear(s);
         init_state(st.p, s);
+    }
+
+    // Deleting R: core[R] = c, then mark the alive vertices within distance h
+    // of R in G[X] (R still alive) into alist, then remove R and update the
+    // alive degrees.
+    void delete_round(int32_t epoch, const int64_t* key) {
+        const int32_t n = g->n;
+        launch_select(key, alive.p, n, st.p, core.p, rlist.p, mark.p, epoch, 0, s);
+        launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
+        launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 0, alist.p, &st.p->aff_fill,
+                      nullptr, s);
+        if (hopfill.p) launch_record_fill(st.p, hopfill.p, 1, s);
+        for (int t = 2; t <= h; ++t) {
+            launch_next_frontier(st.p, s);
+            launch_enqueue(alist.p, &st.p->front_lo, &st.p->front_hi, g->rp, qv.p, qb.p, &st.p->qcount, s);
+            launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 0, alist.p,
+                          &st.p->aff_fill, nullptr, s);
+            if (hopfill.p) launch_record_fill(st.p, hopfill.p, t, s);
+        }
+        launch_kill_list(rlist.p, &st.p->rcount, alive.p, s);
+        launch_set_int(&st.p->qcount, 0, s);
+        launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
+        launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 1, nullptr, nullptr, adeg.p,
+                      s);
+    }
+
+    void trace_round(const RoundState& hs, const char* what, Clock::time_point t0) {
+        if (trace_on() && (hs.rounds < 8 || (hs.rounds & 63) == 0))
+            std::fprintf(stderr, "[kh exact] %s round %d c %lld alive %d removed %d affected %d recomputed %lld t %.3fs\n",
+                         what, hs.rounds, hs.c, hs.alive_count, hs.rcount, hs.aff_fill, recomputed,
+                         std::chrono::duration<double>(Clock::now() - t0).count());
+    }
+
+    // ExactCore with lazy degrees: deg[v] is either exact (exact[v] = 1) or a
+    // lower bound.  A round only commits c = max(c, min deg) when no inexact
+    // vertex has deg <= c; the inexact ones at or below c are recomputed first.
+    // So every deleted vertex has its exact h-degree <= c, and every survivor's
+    // exact h-degree is above c: the same rounds as the eager peel.
+    void run_lazy() {
+        kh_context* ctx = g->ctx;
+        const int32_t n = g->n;
+        const auto t0 = Clock::now();
+        build_items(g, s);
+        alloc(n);
+        exact.alloc(ctx, n);
+        anchor.alloc(ctx, n);
+        hopfill.alloc(ctx, (size_t)h + 2);
+        launch_alive_from(nullptr, alive.p, n, s);
+        launch_alive_degree(g->rp, g->col, alive.p, adeg.p, n, s);
+        launch_fill_i32(mark.p, 0, n, s);
+        launch_fill_i64(core.p, -1, n, s);
+        launch_anchor(nullptr, nullptr, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 0, s);
+        launch_lower_bound(nullptr, nullptr, n, h, alive.p, adeg.p, anchor.p, deg.p, exact.p, s);
+        int32_t epoch = 0;
+        long long iters = 0;
+        for (;;) {
+            if (++iters > 4ll * n + 64) fail(KH_EDEVICE);
+            launch_round_reset(st.p, s);
+            launch_reduce(deg.p, nullptr, alive.p, n, st.p, s);
+            launch_lazy_candidates(alive.p, deg.p, exact.p, n, st.p, srcl.p, 0, 0, s);
+            read_state(ctx, st.p, s);
+            RoundState hs = *ctx->host_state;
+            if (hs.alive_count == 0) break;
+            if (hs.rc_count > 0) {
+                // fill the batch with vertices whose bound is just above c: they are the
+                // next ones to need an exact value, and a sweep costs the same for 1 or
+                // 64 Q sources
+                const int cap = 64 * PL.qmax;
+                int total = hs.rc_count;
+                if (total % cap) {
+                    launch_lazy_candidates(alive.p, deg.p, exact.p, n, st.p, srcl.p, 1,
+                                           (total / cap + 1) * cap, s);
+                    read_state(ctx, st.p, s);
+                    hs = *ctx->host_state;
+                    total += std::min(hs.opt_count, (total / cap + 1) * cap - total);
+                }
+                hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, total, h, deg.p, st.p, s);
+                launch_set_flags(srcl.p, total, exact.p, 1, s);
+                recomputed += total;
+                continue;
+            }
+            ++epoch;
+            launch_round_begin(st.p, nullptr, nullptr, nullptr, 0, s);
+            delete_round(epoch, deg.p);
+            launch_anchor(alist.p, &st.p->aff_fill, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 1, s);
+            launch_decay_bound(alist.p, st.p, hopfill.p, h, alive.p, adeg.p, anchor.p, deg.p, exact.p, s);
+            if (trace_on()) {
+                read_state(ctx, st.p, s);
+                trace_round(*ctx->host_state, "lazy", t0);
+            }
+        }
+        fin = *ctx->host_state;
+        prof_add_counters(ctx, fin);
+    }
+
+    // Replay deleting by a given core map (key); every round records
+    // sum deg_h over the alive set = 2 |E_h(F_K)| (Sec. 6).
+    void run_replay(const uint8_t* alive_in, const int64_t* key) {
+        kh_context* ctx = g->ctx;
+        const int32_t n = g->n;
+        const auto t0 = Clock::now();
+        build_items(g, s);
+        alloc(n);
         launch_alive_from(alive_in, alive.p, n, s);
         launch_alive_degree(g->rp, g->col, alive.p, adeg.p, n, s);
         launch_fill_i32(mark.p, 0, n, s);
         launch_fill_i64(deg.p, 0, n, s);
         launch_fill_i64(core.p, -1, n, s);
-        // initial h-degrees of every alive vertex
         launch_round_reset(st.p, s);
         launch_compact_alive(alive.p, n, srcl.p, &st.p->aff_fill, s);
         read_state(ctx, st.p, s);
         hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, ctx->host_state->aff_fill, h, deg.p, st.p, s);
-        const int64_t* key = key_ext ? key_ext : deg.p;
         int32_t epoch = 0;
-        const auto t_start = Clock::now();
-        if (trace_on())
-            std::fprintf(stderr, "[kh exact] n %d h %d initial degrees %.3fs\n", n, h,
-                         std::chrono::duration<double>(Clock::now() - t_begin).count());
         for (;;) {
             ++epoch;
             launch_round_reset(st.p, s);
             launch_reduce(key, deg.p, alive.p, n, st.p, s);
             launch_round_begin(st.p, ck.p, cs.p, cr.p, 0, s);
-            launch_select(key, alive.p, n, st.p, core.p, rlist.p, mark.p, epoch, 0, s);
-            // vertices within distance h of R in G[X] (R still alive here)
-            launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
-            launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 0, alist.p,
-                          &st.p->aff_fill, nullptr, s);
-            for (int t = 2; t <= h; ++t) {
-                launch_next_frontier(st.p, s);
-                launch_enqueue(alist.p, &st.p->front_lo, &st.p->front_hi, g->rp, qv.p, qb.p, &st.p->qcount, s);
-                launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 0, alist.p,
-                              &st.p->aff_fill, nullptr, s);
-            }
-            launch_kill_list(rlist.p, &st.p->rcount, alive.p, s);
-            launch_set_int(&st.p->qcount, 0, s);
-            launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
-            launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 1, nullptr, nullptr,
-                          adeg.p, s);
+            delete_round(epoch, key);
             read_state(ctx, st.p, s);
             const RoundState hs = *ctx->host_state;
             if (hs.alive_count == 0) break;
-            // every round deletes at least the minimum vertex
             if (hs.rounds > n + 1) fail(KH_EDEVICE);
-            if (trace_on() && (hs.rounds < 8 || (hs.rounds & 63) == 0))
-                std::fprintf(stderr, "[kh exact] round %d c %lld alive %d removed %d affected %d t %.3fs\n", hs.rounds,
-                             hs.c, hs.alive_count, hs.rcount, hs.aff_fill,
-                             std::chrono::duration<double>(Clock::now() - t_start).count());
+            trace_round(hs, "replay", t0);
             if (hs.aff_fill > 0) hdeg_sources(g, PL, alive.p, adeg.p, alist.p, hs.aff_fill, h, deg.p, st.p, s);
         }
         fin = *ctx->host_state;
@@ -720,9 +796,23 @@ struct Lists {
     int hash_log2 = 9;
     std::vector<Buf<int64_t>> cap, off;
     std::vector<Buf<uint32_t>> keys;
-    std::vector<Buf<int32_t>> size;
-    std::vector<Buf<uint8_t>> kk;
+    std::vector<Buf<int32_t>> size, m;
+    std::vector<Buf<uint8_t>> kk, cut, kold;
+    std::vector<Buf<int16_t>> lost;
     std::vector<int64_t> total;
+    LevelView view(int i) const {
+        LevelView L{};
+        if (i < 1 || i > h) return L;
+        L.off = off[i].p;
+        L.keys = keys[i].p;
+        L.size = size[i].p;
+        L.k = kk[i].p;
+        L.m = m[i].p;
+        L.cut = cut[i].p;
+        L.lost = lost[i].p;
+        L.kold = kold[i].p;
+        return L;
+    }
 };
 
 int hash_log2_for(int32_t M) { return std::max(9, ceil_log2(2ll * ((long long)M + 1 + kUnionThreads))); }
@@ -743,7 +833,7 @@ struct SampledRun {
     bool early_stop = false;
     hipStream_t s;
     Buf<uint8_t> alive, rank;
-    Buf<int32_t> mark, rlist, wl, chA, chB, qv, qb, cursor;
+    Buf<int32_t> mark, rlist, wl, rc, lostmax, chA, chB, qv, qb, cursor;
     Buf<int64_t> d, core, ck, cs, cr, partials;
     Buf<RoundState> st;
     Lists L;
@@ -758,6 +848,8 @@ struct SampledRun {
         mark.alloc(ctx, n);
         rlist.alloc(ctx, n);
         wl.alloc(ctx, n);
+        rc.alloc(ctx, n);
+        lostmax.alloc(ctx, n);
         chA.alloc(ctx, n);
         chB.alloc(ctx, n);
         const size_t qcap = (size_t)n + (size_t)(g->nnz / kExpandChunk) + 2;
@@ -784,6 +876,10 @@ struct SampledRun {
         L.keys.resize(h + 1);
         L.size.resize(h + 1);
         L.kk.resize(h + 1);
+        L.m.resize(h + 1);
+        L.cut.resize(h + 1);
+        L.kold.resize(h + 1);
+        L.lost.resize(h + 1);
         L.total.assign(h + 1, 0);
         for (int i = 1; i <= h; ++i) {
             L.cap[i].alloc(ctx, n);
@@ -800,6 +896,10 @@ struct SampledRun {
             L.keys[i].alloc(ctx, (size_t)std::max<int64_t>(tot, 1));
             L.size[i].alloc(ctx, n);
             L.kk[i].alloc(ctx, n);
+            L.m[i].alloc(ctx, n);
+            L.cut[i].alloc(ctx, n);
+            L.kold[i].alloc(ctx, n);
+            L.lost[i].alloc(ctx, n);
         }
         for (int i = 1; i < h; ++i) L.cap[i].release();
         if (h >= 1) L.cap[h].release();
@@ -807,12 +907,10 @@ struct SampledRun {
 
     void init_lists() {
         const int32_t n = g->n;
-        launch_union1(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.off[1].p, L.keys[1].p, L.size[1].p,
-                      L.kk[1].p, nullptr, nullptr, st.p, s);
+        launch_union1(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.view(1), nullptr, nullptr, st.p, s);
         for (int i = 2; i <= h; ++i)
-            launch_union(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2, L.off[i - 1].p,
-                         L.keys[i - 1].p, L.size[i - 1].p, L.kk[i - 1].p, L.off[i].p, L.keys[i].p, L.size[i].p,
-                         L.kk[i].p, cursor.p, nullptr, nullptr, st.p, s);
+            launch_union(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2, L.view(i - 1),
+                         L.view(i), cursor.p, nullptr, nullptr, st.p, s);
         launch_estimate(nullptr, nullptr, n, alive.p, rank.p, L.size[h].p, L.kk[h].p, M, d.p, st.p, s);
     }
 
@@ -824,6 +922,7 @@ struct SampledRun {
         launch_fill_i32(mark.p, 0, g->n, s);
         launch_fill_i64(core.p, -1, g->n, s);
         launch_fill_i64(d.p, 0, g->n, s);
+        launch_fill_i32(lostmax.p, -1, g->n, s);
         build_lists();
         init_lists();
     }
@@ -852,17 +951,16 @@ struct SampledRun {
                     if (i > 1)
                         launch_enqueue(changed[(i - 1) & 1], nullptr, &st.p->changed_count[(i - 1) & 1], g->rp, qv.p,
                                        qb.p, &st.p->qcount, s);
-                    launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 0, wl.p,
-                                  &st.p->wl_count, nullptr, s);
+                    launch_expand_lists(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, rank.p, mark.p, epoch, i,
+                                        L.view(i - 1), L.view(i), lostmax.p, wl.p, &st.p->wl_count, s);
+                    launch_classify(wl.p, &st.p->wl_count, L.view(i), lostmax.p, rc.p, &st.p->rc_count, s);
                     if (i == 1)
-                        launch_union1(wl.p, &st.p->wl_count, n, g->rp, g->col, alive.p, rank.p, M, L.off[1].p,
-                                      L.keys[1].p, L.size[1].p, L.kk[1].p, changed[1], &st.p->changed_count[1], st.p,
-                                      s);
+                        launch_union1(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, L.view(1),
+                                      changed[1], &st.p->changed_count[1], st.p, s);
                     else
-                        launch_union(wl.p, &st.p->wl_count, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2,
-                                     L.off[i - 1].p, L.keys[i - 1].p, L.size[i - 1].p, L.kk[i - 1].p, L.off[i].p,
-                                     L.keys[i].p, L.size[i].p, L.kk[i].p, cursor.p, changed[i & 1],
-                                     &st.p->changed_count[i & 1], st.p, s);
+                        launch_union(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2,
+                                     L.view(i - 1), L.view(i), cursor.p, changed[i & 1], &st.p->changed_count[i & 1],
+                                     st.p, s);
                 }
                 launch_estimate(changed[h & 1], &st.p->changed_count[h & 1], n, alive.p, rank.p, L.size[h].p,
                                 L.kk[h].p, M, d.p, st.p, s);
@@ -872,9 +970,9 @@ struct SampledRun {
             // every round deletes at least the minimum vertex
             if (ctx->host_state->rounds > n + 1) fail(KH_EDEVICE);
             if (trace_on() && ((ctx->host_state->rounds & 255) < batch))
-                std::fprintf(stderr, "[kh sampled] round %d c %lld alive %d removed %d worklist %d t %.3fs\n",
+                std::fprintf(stderr, "[kh sampled] round %d c %lld alive %d removed %d worklist %d merged %d t %.3fs\n",
                              ctx->host_state->rounds, ctx->host_state->c, ctx->host_state->alive_count,
-                             ctx->host_state->rcount, ctx->host_state->wl_count,
+                             ctx->host_state->rcount, ctx->host_state->wl_count, ctx->host_state->rc_count,
                              std::chrono::duration<double>(Clock::now() - t_start).count());
         }
         fin = *ctx->host_state;
@@ -962,12 +1060,26 @@ void dense_sampled(kh_graph* g, const kh_params* P, const int64_t* core_dev, int
 
 void dense_exact(kh_graph* g, const kh_params* P, const int64_t* core_dev, int64_t maxcore, kh_result* res,
                  hipStream_t s) {
+    const bool prune = (P->flags & KH_DENSE_PRUNE) != 0;
     ExactRun E;
     E.g = g;
     E.h = effective_h(g, P->h);
     E.s = s;
-    E.run(nullptr, core_dev);
-    pick_dense(E.cands, (P->flags & KH_DENSE_PRUNE) != 0, 0.0, maxcore, res);
+    Buf<uint8_t> start;
+    const uint8_t* alive_in = nullptr;
+    if (prune) {
+        // exact map: only the innermost level K = max core is a candidate
+        std::vector<int64_t> hc((size_t)g->n);
+        hip_ok(hipMemcpyAsync(hc.data(), core_dev, 8 * (size_t)g->n, hipMemcpyDeviceToHost, s));
+        hip_ok(hipStreamSynchronize(s));
+        std::vector<uint8_t> a((size_t)g->n);
+        for (int32_t v = 0; v < g->n; ++v) a[v] = hc[v] >= maxcore;
+        start.alloc(g->ctx, g->n);
+        hip_ok(hipMemcpyAsync(start.p, a.data(), (size_t)g->n, hipMemcpyHostToDevice, s));
+        alive_in = start.p;
+    }
+    E.run_replay(alive_in, core_dev);
+    pick_dense(E.cands, prune, 0.0, maxcore, res);
     res->edges_traversed += (int64_t)E.fin.te;
     res->arcs_scanned += (int64_t)E.fin.arcs;
 }
@@ -1004,12 +1116,12 @@ extern "C" kh_status kh_core(kh_graph* g, const kh_params* P, int32_t* core_out,
             E.g = g;
             E.h = h;
             E.s = s;
-            E.run(nullptr, nullptr);
+            E.run_lazy();
             finish_core(g->ctx, E.core.p, g->n, core_out, out_dev, s, &R->max_core);
             R->rounds = E.fin.rounds;
             R->edges_traversed = (int64_t)E.fin.te;
             R->arcs_scanned = (int64_t)E.fin.arcs;
-            if (want_dense) pick_dense(E.cands, (P->flags & KH_DENSE_PRUNE) != 0, 0.0, R->max_core, R);
+            if (want_dense) dense_exact(g, P, E.core.p, R->max_core, R, s);
         } else {
             if (g->n > kMaxSampledN) fail(KH_ENOTIMPL);
             SampledRun S;

@@ -43,8 +43,9 @@ struct RoundState {
     int aff_fill;            // affected-list fill
     int wl_count;            // union worklist fill
     int changed_count[2];    // vertices whose (k, B) changed (ping-pong by level parity)
+    int rc_count;            // worklist vertices that must be re-merged / recomputed
+    int opt_count;           // optional recomputations appended to a batch
     int overflow;            // an estimate exceeded the representable range
-    int pad;
     unsigned long long te;     // edges traversed (exact h-degree work)
     unsigned long long arcs;   // adjacency entries read by the h-degree kernels
     unsigned long long elems;  // sample-list entries read by the union kernels
@@ -95,6 +96,24 @@ void launch_level_reset(RoundState* st, int level, hipStream_t s);
 void launch_set_int(int* p, int v, hipStream_t s);
 void launch_scan_i64(const int64_t* in, int64_t* out, int32_t n, int64_t* partials, hipStream_t s);
 void launch_core_to_i32(const int64_t* core, int32_t* out, int32_t n, int* overflow, hipStream_t s);
+// anchor[v] = alive neighbour of largest alive degree (smallest id on ties), -1 if none;
+// list == NULL: all vertices; only_dead: refresh only anchors that were deleted.
+void launch_anchor(const int32_t* list, const int* count, int32_t n, const int32_t* rp, const int32_t* col,
+                   const uint8_t* alive, const int32_t* adeg, int32_t* anchor, int only_dead, hipStream_t s);
+// deg[v] = a lower bound of deg_h(v;X) (alive degrees along the anchor chain), exact[v] = (h == 1).
+void launch_lower_bound(const int32_t* list, const int* count, int32_t n, int h, const uint8_t* alive,
+                        const int32_t* adeg, const int32_t* anchor, int64_t* deg, uint8_t* exact, hipStream_t s);
+// After deleting R: for the affected vertex alist[i] found at BFS hop t,
+// deg <- max(deg - |N(R; h-t)|, anchor bound), exact = (h == 1).  hopfill[t] = affected
+// vertices found in hops 1..t.
+void launch_decay_bound(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
+                        const int32_t* adeg, const int32_t* anchor, int64_t* deg, uint8_t* exact, hipStream_t s);
+void launch_record_fill(RoundState* st, int* hopfill, int t, hipStream_t s);
+// pass 0: out[0..rc_count) = {alive v : !exact[v], deg[v] <= c'}, c' = max(c, min key);
+// pass 1: out[rc_count + i] for i < opt_cap - rc_count: inexact v with c' < deg[v] <= c' + c'/8 + 32.
+void launch_lazy_candidates(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
+                            int32_t* out, int pass, int opt_cap, hipStream_t s);
+void launch_set_flags(const int32_t* list, int count, uint8_t* flags, uint8_t v, hipStream_t s);
 
 // ---- kernels: bit-parallel multi-source bounded BFS (kh_msbfs.hip) ---------------------
 
@@ -131,19 +150,39 @@ void ms_batch(const MsPlanes& P, const MsItems& I, int32_t n, const int32_t* rp,
 
 // ---- kernels: sampled lists (kh_union.hip) ---------------------------------------------
 
+// Device arrays of one level i of the sampled lists.
+struct LevelView {
+    const int64_t* off;  // n+1 list offsets (capacity bounds)
+    uint32_t* keys;      // list entries
+    int32_t* size;       // |B[v,i]|
+    uint8_t* k;          // k[v,i]
+    int32_t* m;          // alive neighbours w with k[w,i-1] == k[v,i]
+    uint8_t* cut;        // 1 if k[v,i] was set by the M threshold (k > max_w k[w,i-1])
+    int16_t* lost;       // for vertices changed this round: highest rank that left B[v,i] (-1: none)
+    uint8_t* kold;       // for vertices changed this round: k[v,i] before the change
+};
+
 void launch_cap_level1(const int32_t* rp, int32_t n, int32_t M, int64_t* cap, hipStream_t s);
 void launch_cap_next(const int32_t* rp, const int32_t* col, int32_t n, int32_t M, const int64_t* cap_prev,
                      int64_t* cap, hipStream_t s);
-// Level 1 (neighbour lists are singletons).  worklist == NULL: all vertices.
+// Level 1 (neighbour lists are singletons).  worklist == NULL: all vertices (initialisation).
 void launch_union1(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
-                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int64_t* off, uint32_t* keys,
-                   int32_t* size, uint8_t* kk, int32_t* changed, int* changed_count, RoundState* st, hipStream_t s);
+                   const uint8_t* alive, const uint8_t* rank, int32_t M, LevelView cur, int32_t* changed,
+                   int* changed_count, RoundState* st, hipStream_t s);
 // Level i >= 2.
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
-                  const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, const int64_t* off_prev,
-                  const uint32_t* keys_prev, const int32_t* size_prev, const uint8_t* k_prev, const int64_t* off,
-                  uint32_t* keys, int32_t* size, uint8_t* kk, int32_t* cursor, int32_t* changed, int* changed_count,
-                  RoundState* st, hipStream_t s);
+                  const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, LevelView prev, LevelView cur,
+                  int32_t* cursor, int32_t* changed, int* changed_count, RoundState* st, hipStream_t s);
+// Propagate the deletions and changes of level i-1 over the arcs of the queued
+// vertices: mark + append alive neighbours, fold the highest lost rank into
+// lostmax[], and keep m[.,i] current.
+void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp,
+                         const int32_t* col, const uint8_t* alive, const uint8_t* rank, int32_t* mark, int32_t epoch,
+                         int level, LevelView prev, LevelView cur, int32_t* lostmax, int32_t* out, int* out_count,
+                         hipStream_t s);
+// Keep only the worklist vertices whose list can change.
+void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int32_t* lostmax, int32_t* rc,
+                     int* rc_count, hipStream_t s);
 // Alg. 1 estimate from level h.  worklist == NULL: all vertices.
 void launch_estimate(const int32_t* worklist, const int* wl_count, int32_t n, const uint8_t* alive,
                      const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, int64_t* d,

@@ -140,21 +140,64 @@ __global__ __launch_bounds__(256) void k_ms_pull(int32_t nitems, const int32_t* 
         const int32_t b = item_beg[it], e = item_end[it];
         uint64_t a = 0ull;
         int32_t p = b;
-        while (p < e) {
-            const int32_t w = col[p];
-            if ((bm_cur[w >> 5] >> (w & 31)) & 1u) {
-                a |= fr_cur[(size_t)w * Q + j];
-                if (j == 0) gath += 8 * Q;
+        if (Q >= 4) {
+            // Q adjacency ids per chunk (lane j reads arc base + j), their frontier
+            // bits tested in parallel, then the group gathers word j of every
+            // frontier neighbour, four loads in flight at a time
+            for (; p < e; p += Q) {
+                const int32_t pj = p + j;
+                int32_t w = 0;
+                bool f = false;
+                if (pj < e) {
+                    w = col[pj];
+                    f = (bm_cur[w >> 5] >> (w & 31)) & 1u;
+                }
+                unsigned long long fm = (__ballot(f) & gmask) >> gbase;
+                if (j == 0) gath += (unsigned long long)__popcll(fm) * 8 * Q;
+                while (fm) {
+                    int32_t ws[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ws[u] = -1;
+                        if (fm) {
+                            const int k = __ffsll((long long)fm) - 1;
+                            fm &= fm - 1ull;
+                            ws[u] = __shfl(w, gbase + k);
+                        }
+                    }
+                    uint64_t x[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) x[u] = ws[u] >= 0 ? fr_cur[(size_t)ws[u] * Q + j] : 0ull;
+                    a |= x[0] | x[1] | x[2] | x[3];
+                }
+                const bool full = ((a | vw) & vm) == vm;
+                if ((__ballot(full) & gmask) == gmask) {
+                    p = min(p + Q, e);
+                    break;
+                }
             }
-            ++p;
-            if (((p - b) & 15) == 0) {
-                const bool f = ((a | vw) & vm) == vm;
-                if ((__ballot(f) & gmask) == gmask) break;
+            if (p > e) p = e;
+        } else {
+            // narrow groups: four independent arcs per step
+            while (p < e) {
+                int32_t w[4];
+                bool f[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    w[u] = p + u < e ? col[p + u] : -1;
+                    f[u] = w[u] >= 0 && ((bm_cur[w[u] >> 5] >> (w[u] & 31)) & 1u);
+                }
+                uint64_t x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = f[u] ? fr_cur[(size_t)w[u] * Q + j] : 0ull;
+                a |= x[0] | x[1] | x[2] | x[3];
+                if (j == 0) gath += (unsigned long long)(f[0] + f[1] + f[2] + f[3]) * 8 * Q;
+                p = min(p + 4, e);
+                if (((p - b) & 15) == 0) {
+                    const bool full = ((a | vw) & vm) == vm;
+                    if ((__ballot(full) & gmask) == gmask) break;
+                }
             }
-        }
-        if (j == 0) {
-            arcs += (unsigned long long)(p - b);
-            bytes += 4ull * (unsigned long long)(p - b);  // col[]
         }
         if (item_split[it]) {
             const uint64_t nw = a & ~vw & vm;
@@ -187,7 +230,23 @@ __global__ __launch_bounds__(256) void k_ms_pull(int32_t nitems, const int32_t* 
 }
 
 // Column popcounts of vis: cnt[j] += #{u : bit j of vis[u]}; vis is cleared on the way.
-// A wave takes 64 vertices; lane b keeps the count of bit b of each word.
+// A wave takes 64 vertices (lane = vertex) and, per word, transposes the 64x64
+// bit matrix across lanes with six shuffle-and-mask steps, after which lane b
+// holds bit b of all 64 vertices and one popcount counts it.
+__device__ __forceinline__ uint64_t transpose64(uint64_t x, int l) {
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+        const int sft = 32 >> t;
+        const uint64_t m = masks[t];
+        const uint64_t y = __shfl_xor(x, sft);
+        if (l & sft) x = (x & ~m) | ((y >> sft) & m);
+        else x = (x & m) | ((y & m) << sft);
+    }
+    return x;
+}
+
 template <int Q>
 __global__ void k_ms_count(int32_t n, uint64_t* __restrict__ vis, uint32_t* __restrict__ cnt) {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -204,21 +263,15 @@ __global__ void k_ms_count(int32_t n, uint64_t* __restrict__ vis, uint32_t* __re
         for (int q = 0; q < Q; ++q) w[q] = 0ull;
         if (u < n) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                w[q] = vis[(size_t)u * Q + q];
+            for (int q = 0; q < Q; ++q) w[q] = vis[(size_t)u * Q + q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
                 if (w[q]) vis[(size_t)u * Q + q] = 0ull;
-            }
         }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            uint64_t present = w[q];
-            for (int o = 32; o > 0; o >>= 1) present |= __shfl_xor(present, o);
-            while (present) {
-                const int b = __ffsll((long long)present) - 1;
-                present &= present - 1ull;
-                const unsigned long long m = __ballot((w[q] >> b) & 1ull);
-                if (l == b) c[q] += (uint32_t)__popcll(m);
-            }
+            if (__ballot(w[q] != 0ull) == 0ull) continue;
+            c[q] += (uint32_t)__popcll(transpose64(w[q], l));
         }
     }
 #pragma unroll

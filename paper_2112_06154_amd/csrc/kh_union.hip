@@ -21,6 +21,8 @@
 
 namespace kh {
 
+__device__ __forceinline__ uint32_t* keys_at(const LevelView& L, int32_t v) { return L.keys + L.off[v]; }
+
 __global__ void k_cap_level1(const int32_t* __restrict__ rp, int32_t n, int32_t M, int64_t* __restrict__ cap) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int64_t c = 1 + (int64_t)(rp[v + 1] - rp[v]);
@@ -58,14 +60,16 @@ void launch_cap_next(const int32_t* rp, const int32_t* col, int32_t n, int32_t M
 }
 
 // ---- level 1: T = {v} + alive neighbours (all distinct) -------------------------------------
+// Besides B[v,1] and k[v,1] this writes m[v,1] (alive neighbours with
+// k[w,0] = 0 = k[v,1]), the cut flag (k[v,1] > 0), and for a changed list the
+// highest rank that left it (a member leaves exactly when it was deleted).
 __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ worklist, const int* wl_count, int32_t n,
                                                 const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                 const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
-                                                int32_t M, const int64_t* __restrict__ off, uint32_t* __restrict__ keys,
-                                                int32_t* __restrict__ size, uint8_t* __restrict__ kk,
-                                                int32_t* __restrict__ changed, int* changed_count, RoundState* st) {
+                                                int32_t M, LevelView cur, int32_t* __restrict__ changed,
+                                                int* changed_count, RoundState* st) {
     __shared__ int hist[256];
-    __shared__ int s_k, s_size;
+    __shared__ int s_k, s_size, s_nb, s_ok, s_os, s_lost;
     const int tid = threadIdx.x;
     const int total = worklist ? *wl_count : n;
     unsigned long long elems = 0;
@@ -74,6 +78,11 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
         if (!alive[v]) continue;
         const int32_t b = rp[v], e = rp[v + 1];
         hist[tid] = 0;
+        if (tid == 0) {
+            s_ok = cur.k[v];
+            s_os = cur.size[v];
+            s_lost = -1;
+        }
         __syncthreads();
         for (int32_t p = b + tid; p < e; p += blockDim.x) {
             const int32_t w = col[p];
@@ -84,7 +93,8 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
         __syncthreads();
         if (tid == 0) {
             // k = smallest level whose suffix count is <= M
-            int run = 0, k = 0;
+            int run = 0, k = 0, all = 0;
+            for (int L = 0; L < 256; ++L) all += hist[L];
             for (int L = 255; L >= 0; --L) {
                 if (run + hist[L] > M) {
                     k = L + 1;
@@ -100,10 +110,22 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
             }
             s_k = k;
             s_size = run;
+            s_nb = all - 1;
         }
         __syncthreads();
         const int k = s_k;
-        uint32_t* out = keys + off[v];
+        const bool chg = changed && (s_ok != k || s_os != s_size);
+        uint32_t* out = keys_at(cur, v);
+        if (chg) {
+            int lm = -1;
+            for (int t = tid; t < s_os; t += blockDim.x) {
+                const uint32_t key = out[t];
+                if (!alive[key & 0xFFFFFFu]) lm = max(lm, key_rank(key));
+            }
+            lm = wave_max_i(lm);
+            if (lane_id() == 0 && lm >= 0) atomicMax(&s_lost, lm);
+            __syncthreads();
+        }
         for (int32_t p = b + tid; p < e; p += blockDim.x) {
             const int32_t w = col[p];
             if (alive[w]) {
@@ -114,10 +136,15 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
         if (tid == 0) {
             const int rv = rank[v];
             if (rv >= k) out[atomicAdd(&hist[rv], 1)] = sample_key(rv, v);
-            const int ok = kk[v], os = size[v];
-            size[v] = s_size;
-            kk[v] = (uint8_t)k;
-            if (changed && (ok != k || os != s_size)) changed[atomicAdd(changed_count, 1)] = v;
+            cur.size[v] = s_size;
+            cur.k[v] = (uint8_t)k;
+            cur.m[v] = k == 0 ? s_nb : 0;
+            cur.cut[v] = k > 0 ? 1 : 0;
+            if (chg) {
+                cur.lost[v] = (int16_t)s_lost;
+                cur.kold[v] = (uint8_t)s_ok;
+                changed[atomicAdd(changed_count, 1)] = v;
+            }
         }
         __syncthreads();
     }
@@ -126,12 +153,12 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
 }
 
 void launch_union1(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
-                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int64_t* off, uint32_t* keys,
-                   int32_t* size, uint8_t* kk, int32_t* changed, int* changed_count, RoundState* st, hipStream_t s) {
+                   const uint8_t* alive, const uint8_t* rank, int32_t M, LevelView cur, int32_t* changed,
+                   int* changed_count, RoundState* st, hipStream_t s) {
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
-    hipLaunchKernelGGL(k_union1, dim3(grid), dim3(256), 0, s, worklist, wl_count, n, rp, col, alive, rank, M, off, keys,
-                       size, kk, changed, changed_count, st);
+    hipLaunchKernelGGL(k_union1, dim3(grid), dim3(256), 0, s, worklist, wl_count, n, rp, col, alive, rank, M, cur,
+                       changed, changed_count, st);
 }
 
 // ---- levels i >= 2 ----------------------------------------------------------------------
@@ -141,18 +168,18 @@ struct HashSet {
     int shift;
     int* count;
     int* hist;
-    int* over;
     int M;
 };
 
+__device__ __forceinline__ uint32_t hs_slot(const HashSet& H, uint32_t key) { return (key * 2654435761u) >> H.shift; }
+
 __device__ __forceinline__ void hs_insert(const HashSet& H, uint32_t key) {
-    uint32_t h = (key * 2654435761u) >> H.shift;
+    uint32_t h = hs_slot(H, key);
     for (;;) {
         const uint32_t old = atomicCAS(&H.tab[h], kEmptyKey, key);
         if (old == kEmptyKey) {
-            const int c = atomicAdd(H.count, 1) + 1;
+            atomicAdd(H.count, 1);
             atomicAdd(&H.hist[key_rank(key)], 1);
-            if (c > H.M) *(volatile int*)H.over = 1;
             return;
         }
         if (old == key) return;
@@ -160,23 +187,34 @@ __device__ __forceinline__ void hs_insert(const HashSet& H, uint32_t key) {
     }
 }
 
+__device__ __forceinline__ bool hs_contains(const HashSet& H, uint32_t key) {
+    uint32_t h = hs_slot(H, key);
+    for (;;) {
+        const uint32_t x = H.tab[h];
+        if (x == key) return true;
+        if (x == kEmptyKey) return false;
+        h = (h + 1u) & H.mask;
+    }
+}
+
+// Besides B[v,i] and k[v,i] this writes m[v,i] (alive neighbours whose
+// k[w,i-1] equals the new k[v,i]), the cut flag (k[v,i] above every
+// neighbour's level, i.e. fixed by the M threshold), and for a changed list the
+// highest rank among its members that are not in the new list.
 __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ worklist, const int* wl_count, int32_t n,
                                                const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
-                                               int32_t M, int hash_log2, const int64_t* __restrict__ off_prev,
-                                               const uint32_t* __restrict__ keys_prev,
-                                               const int32_t* __restrict__ size_prev,
-                                               const uint8_t* __restrict__ k_prev, const int64_t* __restrict__ off,
-                                               uint32_t* __restrict__ keys, int32_t* __restrict__ size,
-                                               uint8_t* __restrict__ kk, int32_t* __restrict__ cursor,
-                                               int32_t* __restrict__ changed, int* changed_count, RoundState* st) {
+                                               int32_t M, int hash_log2, LevelView prev, LevelView cur,
+                                               int32_t* __restrict__ cursor, int32_t* __restrict__ changed,
+                                               int* changed_count, RoundState* st) {
     extern __shared__ uint32_t tab[];
     __shared__ int hist[256];
-    __shared__ int s_kmax, s_htop, s_count, s_over, s_k, s_size;
+    __shared__ int hk[256];
+    __shared__ int s_kmax, s_htop, s_count, s_k, s_size, s_ok, s_os, s_lost;
     const int tid = threadIdx.x;
     const int bs = blockDim.x;
     const int hcap = 1 << hash_log2;
-    HashSet H{tab, (uint32_t)(hcap - 1), 32 - hash_log2, &s_count, hist, &s_over, M};
+    HashSet H{tab, (uint32_t)(hcap - 1), 32 - hash_log2, &s_count, hist, M};
     const int total = worklist ? *wl_count : n;
     unsigned long long elems = 0;
     for (int wi = blockIdx.x; wi < total; wi += gridDim.x) {
@@ -185,11 +223,14 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
         const int32_t b = rp[v], e = rp[v + 1];
         for (int t = tid; t < hcap; t += bs) tab[t] = kEmptyKey;
         hist[tid] = 0;
+        hk[tid] = 0;
         if (tid == 0) {
             s_kmax = 0;
             s_htop = rank[v];
             s_count = 0;
-            s_over = 0;
+            s_ok = cur.k[v];
+            s_os = cur.size[v];
+            s_lost = -1;
         }
         __syncthreads();
         int kmax_l = 0, htop_l = -1;
@@ -197,10 +238,11 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             const int32_t w = col[p];
             cursor[p] = 0;
             if (alive[w]) {
-                const int kw = k_prev[w];
+                const int kw = prev.k[w];
+                atomicAdd(&hk[kw], 1);
                 kmax_l = kw > kmax_l ? kw : kmax_l;
-                if (size_prev[w] > 0) {
-                    const int hr = key_rank(keys_prev[off_prev[w]]);
+                if (prev.size[w] > 0) {
+                    const int hr = key_rank(prev.keys[prev.off[w]]);
                     htop_l = hr > htop_l ? hr : htop_l;
                 }
             }
@@ -219,9 +261,9 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
                 const int32_t w = col[p];
                 if (!alive[w]) continue;
                 int c = cursor[p];
-                const int sz = size_prev[w];
+                const int sz = prev.size[w];
                 if (c >= sz) continue;
-                const uint32_t* lst = keys_prev + off_prev[w];
+                const uint32_t* lst = prev.keys + prev.off[w];
                 const int c0 = c;
                 while (c < sz) {
                     const uint32_t key = lst[c];
@@ -236,7 +278,7 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             }
             if (tid == 0 && rank[v] == L && *(volatile int*)&s_count <= M) hs_insert(H, sample_key(L, v));
             __syncthreads();
-            const int over = s_over;
+            const int over = s_count > M;
             __syncthreads();
             if (over) {
                 k = L + 1;
@@ -254,7 +296,21 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             s_size = run;
         }
         __syncthreads();
-        uint32_t* out = keys + off[v];
+        const bool chg = changed && (s_ok != s_k || s_os != s_size);
+        uint32_t* out = keys_at(cur, v);
+        if (chg) {
+            // members of the old list that are not in the new one (the old list is
+            // still in place: every old member has rank >= old k >= new k, so it is
+            // in the table exactly when it is still in the list)
+            int lm = -1;
+            for (int t = tid; t < s_os; t += bs) {
+                const uint32_t key = out[t];
+                if (!hs_contains(H, key)) lm = max(lm, key_rank(key));
+            }
+            lm = wave_max_i(lm);
+            if (lane_id() == 0 && lm >= 0) atomicMax(&s_lost, lm);
+            __syncthreads();
+        }
         for (int t = tid; t < hcap; t += bs) {
             const uint32_t key = tab[t];
             if (key != kEmptyKey) {
@@ -263,10 +319,15 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             }
         }
         if (tid == 0) {
-            const int ok = kk[v], os = size[v];
-            size[v] = s_size;
-            kk[v] = (uint8_t)s_k;
-            if (changed && (ok != s_k || os != s_size)) changed[atomicAdd(changed_count, 1)] = v;
+            cur.size[v] = s_size;
+            cur.k[v] = (uint8_t)s_k;
+            cur.m[v] = hk[s_k];
+            cur.cut[v] = s_k > kmax ? 1 : 0;
+            if (chg) {
+                cur.lost[v] = (int16_t)s_lost;
+                cur.kold[v] = (uint8_t)s_ok;
+                changed[atomicAdd(changed_count, 1)] = v;
+            }
         }
         __syncthreads();
     }
@@ -275,10 +336,8 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
 }
 
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
-                  const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, const int64_t* off_prev,
-                  const uint32_t* keys_prev, const int32_t* size_prev, const uint8_t* k_prev, const int64_t* off,
-                  uint32_t* keys, int32_t* size, uint8_t* kk, int32_t* cursor, int32_t* changed, int* changed_count,
-                  RoundState* st, hipStream_t s) {
+                  const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, LevelView prev, LevelView cur,
+                  int32_t* cursor, int32_t* changed, int* changed_count, RoundState* st, hipStream_t s) {
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
     const size_t lds = sizeof(uint32_t) << hash_log2;
@@ -288,8 +347,95 @@ void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const
         lds_set = lds;
     }
     hipLaunchKernelGGL(k_union, dim3(grid), dim3(kUnionThreads), lds, s, worklist, wl_count, n, rp, col, alive, rank,
-                       M, hash_log2, off_prev, keys_prev, size_prev, k_prev, off, keys, size, kk, cursor, changed,
-                       changed_count, st);
+                       M, hash_log2, prev, cur, cursor, changed, changed_count, st);
+}
+
+// ---- propagation of deletions and changes to the next level ---------------------------------
+// For an arc w -> v with v alive and w deleted or changed at level i-1:
+//   * every member B[w,i-1] lost (all of it when w was deleted) may leave
+//     B[v,i]; the highest such rank goes into lostmax[v];
+//   * if k[w,i-1] was equal to k[v,i] and w was deleted or its level dropped,
+//     m[v,i] loses one (the paper's m counter, Sec. 5).
+__global__ void k_expand_lists(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
+                               const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                               const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
+                               int32_t* __restrict__ mark, int32_t epoch, int level, LevelView prev, LevelView cur,
+                               int32_t* __restrict__ lostmax, int32_t* __restrict__ out, int* out_count) {
+    const int nq = *qcount;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int l = lane_id();
+    for (int q = wave; q < nq; q += nwaves) {
+        const int32_t w = qv[q];
+        const int32_t b = qb[q];
+        const int32_t e = min(b + kExpandChunk, rp[w + 1]);
+        const bool removed = !alive[w];
+        int lw, kw_old, kw_new;
+        if (level == 1) {
+            lw = rank[w];  // B[w,0] = {w}; only deleted vertices reach level 1
+            kw_old = kw_new = 0;
+        } else if (removed) {
+            lw = prev.size[w] > 0 ? key_rank(prev.keys[prev.off[w]]) : -1;
+            kw_old = kw_new = prev.k[w];
+        } else {
+            lw = prev.lost[w];
+            kw_old = prev.kold[w];
+            kw_new = prev.k[w];
+        }
+        const bool dec_any = removed || kw_new < kw_old;
+        for (int32_t p0 = b; p0 < e; p0 += 64) {
+            const int32_t p = p0 + l;
+            bool want = false;
+            int32_t v = 0;
+            if (p < e) {
+                v = col[p];
+                if (alive[v]) {
+                    if (lw >= 0 && lostmax[v] < lw) atomicMax(&lostmax[v], lw);
+                    if (dec_any && cur.k[v] == kw_old) atomicSub(&cur.m[v], 1);
+                    if (mark[v] != epoch) want = atomicExch(&mark[v], epoch) != epoch;
+                }
+            }
+            const int slot = wave_append_slot(want, out_count);
+            if (want) out[slot] = v;
+        }
+    }
+}
+void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp,
+                         const int32_t* col, const uint8_t* alive, const uint8_t* rank, int32_t* mark, int32_t epoch,
+                         int level, LevelView prev, LevelView cur, int32_t* lostmax, int32_t* out, int* out_count,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_expand_lists, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, rank, mark, epoch,
+                       level, prev, cur, lostmax, out, out_count);
+}
+
+// A list can only change when (cut) a member of rank >= k-1 left some input
+// list -- otherwise |N(v;i)| at ranks >= k-1 still exceeds M, k stays and no
+// member left; or (not cut, m > 0) a member of rank >= k left -- k cannot drop
+// while a neighbour sits at level k; or (not cut, m = 0) always.
+__global__ void k_classify(const int32_t* __restrict__ wl, const int* wl_count, LevelView cur,
+                           int32_t* __restrict__ lostmax, int32_t* __restrict__ rc, int* rc_count) {
+    const int total = *wl_count;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < total; base += stride) {
+        const int i = base + threadIdx.x;
+        bool need = false;
+        int32_t v = 0;
+        if (i < total) {
+            v = wl[i];
+            const int k = cur.k[v];
+            const int L = lostmax[v];
+            lostmax[v] = -1;
+            if (cur.cut[v]) need = L >= k - 1;
+            else if (cur.m[v] > 0) need = L >= k;
+            else need = true;
+        }
+        const int slot = wave_append_slot(need, rc_count);
+        if (need) rc[slot] = v;
+    }
+}
+void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int32_t* lostmax, int32_t* rc,
+                     int* rc_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_classify, dim3(1024), dim3(256), 0, s, wl, wl_count, cur, lostmax, rc, rc_count);
 }
 
 // ---- Alg. 1: d = |B[v,h] \ {v}| 2^k, and max(d, M 2^(k-1)) when k > 0 ---------------------------
