@@ -174,14 +174,20 @@ __global__ void k_round_reset(RoundState* st) {
     st->changed_count[1] = 0;
     st->rc_count = 0;
     st->opt_count = 0;
+    st->ms_ns = 0;
+    for (int b = 0; b < 48; ++b) st->hist[b] = 0;
+    st->fcount[0] = 0;
+    st->fcount[1] = 0;
 }
 void launch_round_reset(RoundState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, s, st);
 }
 
-// min of key, sum of val and count over alive vertices.
-__global__ void k_reduce(const int64_t* __restrict__ key, const int64_t* __restrict__ val,
-                         const uint8_t* __restrict__ alive, int32_t n, RoundState* st) {
+// min of key, sum of val and count over alive vertices (one atomic triple per block).
+__global__ __launch_bounds__(512) void k_reduce(const int64_t* __restrict__ key, const int64_t* __restrict__ val,
+                                                const uint8_t* __restrict__ alive, int32_t n, RoundState* st) {
+    __shared__ long long smin[8], ssum[8];
+    __shared__ int scnt[8];
     long long mn = LLONG_MAX, sm = 0;
     int cnt = 0;
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
@@ -195,15 +201,29 @@ __global__ void k_reduce(const int64_t* __restrict__ key, const int64_t* __restr
     mn = wave_min_ll(mn);
     sm = wave_sum_ll(sm);
     cnt = wave_sum_i(cnt);
-    if (lane_id() == 0 && cnt > 0) {
-        atomicMin(&st->min_key, mn);
-        atomicAdd((unsigned long long*)&st->sum_val, (unsigned long long)sm);
-        atomicAdd(&st->alive_count, cnt);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        smin[w] = mn;
+        ssum[w] = sm;
+        scnt[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            mn = smin[i] < mn ? smin[i] : mn;
+            sm += ssum[i];
+            cnt += scnt[i];
+        }
+        if (cnt > 0) {
+            atomicMin(&st->min_key, mn);
+            if (sm) atomicAdd((unsigned long long*)&st->sum_val, (unsigned long long)sm);
+            atomicAdd(&st->alive_count, cnt);
+        }
     }
 }
 void launch_reduce(const int64_t* key, const int64_t* val, const uint8_t* alive, int32_t n, RoundState* st,
                    hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_reduce, dim3(grid_for(n, 256, 2048)), dim3(256), 0, s, key, val, alive, n, st);
+    if (n > 0) hipLaunchKernelGGL(k_reduce, dim3(grid_for(n, 512, 256)), dim3(512), 0, s, key, val, alive, n, st);
 }
 
 // c = max(c, min key).  When c rises to K, the alive set is exactly
@@ -610,6 +630,253 @@ __global__ void k_set_flags(const int32_t* __restrict__ list, int count, uint8_t
 }
 void launch_set_flags(const int32_t* list, int count, uint8_t* flags, uint8_t v, hipStream_t s) {
     if (count > 0) hipLaunchKernelGGL(k_set_flags, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, list, count, flags, v);
+}
+
+// ---- device-driven rounds of the lazy exact peel -------------------------------------------
+__device__ __forceinline__ long long cur_level(const RoundState* st) {
+    return st->min_key > st->c ? st->min_key : st->c;
+}
+
+// hist[b] = inexact alive vertices with bound - c' in bucket b (c' = max(c, min)).
+__global__ void k_bound_hist(const uint8_t* __restrict__ alive, const int64_t* __restrict__ deg,
+                             const uint8_t* __restrict__ exact, int32_t n, RoundState* st) {
+    __shared__ int h[48];
+    if (threadIdx.x < 48) h[threadIdx.x] = 0;
+    __syncthreads();
+    if (st->alive_count > 0) {
+        const long long c = cur_level(st);
+        for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+            if (alive[v] && !exact[v]) {
+                const long long d = deg[v] - c;
+                const int b = d <= 0 ? 0 : min(47, 64 - __clzll((unsigned long long)d));
+                atomicAdd(&h[b], 1);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 48 && h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
+}
+void launch_bound_hist(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
+                       hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_bound_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, alive, deg, exact, n, st);
+}
+
+// Commit the round when no inexact vertex is at or below c'; otherwise recompute
+// the cap inexact vertices with the smallest bounds (whole buckets).
+__global__ void k_decide(RoundState* st, int cap) {
+    if (st->alive_count == 0) {
+        st->mode = 2;
+        return;
+    }
+    const long long c = cur_level(st);
+    if (st->hist[0] == 0) {
+        st->mode = 0;
+        return;
+    }
+    st->mode = 1;
+    int acc = st->hist[0], B = 0;
+    for (int b = 1; b < 48; ++b) {
+        if (acc + st->hist[b] > cap) break;
+        acc += st->hist[b];
+        B = b;
+    }
+    st->hi = B == 0 ? c : c + ((1ll << B) - 1);
+}
+void launch_decide(RoundState* st, int cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(1), 0, s, st, cap);
+}
+
+__global__ void k_pick(const uint8_t* __restrict__ alive, const int64_t* __restrict__ deg,
+                       const uint8_t* __restrict__ exact, int32_t n, RoundState* st, int32_t* __restrict__ out,
+                       int cap) {
+    if (st->mode != 1) return;
+    const long long hi = st->hi;
+    const int32_t stride = gridDim.x * blockDim.x;
+    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        if (*(volatile int*)&st->rc_count >= cap) break;
+        const int32_t v = base + threadIdx.x;
+        const bool want = v < n && alive[v] && !exact[v] && deg[v] <= hi;
+        const int slot = wave_append_slot(want, &st->rc_count);
+        if (want && slot < cap) out[slot] = v;
+    }
+}
+__global__ void k_pick_finish(RoundState* st, int cap) {
+    if (st->mode == 1) st->ms_ns = st->rc_count < cap ? st->rc_count : cap;
+}
+void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
+                 int32_t* out, int cap, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_pick, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, alive, deg, exact, n, st, out, cap);
+    hipLaunchKernelGGL(k_pick_finish, dim3(1), dim3(1), 0, s, st, cap);
+}
+
+__global__ void k_mark_exact(const int32_t* __restrict__ list, RoundState* st, uint8_t* __restrict__ exact) {
+    const int cnt = st->ms_ns;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) exact[list[i]] = 1;
+}
+void launch_mark_exact(const int32_t* list, RoundState* st, uint8_t* exact, hipStream_t s) {
+    hipLaunchKernelGGL(k_mark_exact, dim3(4), dim3(256), 0, s, list, st, exact);
+}
+
+__global__ void k_round_begin_gated(RoundState* st) {
+    if (st->mode != 0) return;
+    const long long c = cur_level(st);
+    st->c = c;
+    st->rounds += 1;
+}
+void launch_round_begin_gated(RoundState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_begin_gated, dim3(1), dim3(1), 0, s, st);
+}
+
+__global__ void k_select_gated(const int64_t* __restrict__ key, uint8_t* __restrict__ alive, int32_t n, RoundState* st,
+                               int64_t* __restrict__ core, int32_t* __restrict__ rlist, int32_t* __restrict__ mark,
+                               int32_t epoch) {
+    if (st->mode != 0) return;
+    const long long c = st->c;
+    const int32_t stride = gridDim.x * blockDim.x;
+    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int32_t v = base + threadIdx.x;
+        const bool take = v < n && alive[v] && key[v] <= c;
+        const int slot = wave_append_slot(take, &st->rcount);
+        if (take) {
+            core[v] = c;
+            rlist[slot] = v;
+            mark[v] = epoch;
+        }
+    }
+}
+void launch_select_gated(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core, int32_t* rlist,
+                         int32_t* mark, int32_t epoch, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_select_gated, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, key, alive, n, st, core,
+                           rlist, mark, epoch);
+}
+
+// ---- R-mask BFS of the lazy exact peel ---------------------------------------------------------
+// For v at distance exactly h from R, every vertex that leaves N(v;h,X) when R is
+// deleted is itself in R (a path that needed R reaches it after h steps), so
+// deg_h(v; X \ R) = deg_h(v; X) - |R ∩ N(v;h,X)|: an exact update.  The mask BFS
+// gives |R ∩ N(v;h,X)| as a popcount when |R| <= 64.
+__global__ void k_rbfs_init(const int32_t* __restrict__ rlist, RoundState* st, uint64_t* __restrict__ rmask,
+                            uint64_t* __restrict__ gain) {
+    const int cnt = st->rcount;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
+        const int32_t r = rlist[j];
+        const unsigned long long b = 1ull << (j & 63);
+        atomicOr((unsigned long long*)&rmask[r], b);
+        atomicOr((unsigned long long*)&gain[r], b);
+    }
+}
+void launch_rbfs_init(const int32_t* rlist, RoundState* st, uint64_t* rmask, uint64_t* gain, hipStream_t s) {
+    hipLaunchKernelGGL(k_rbfs_init, dim3(64), dim3(256), 0, s, rlist, st, rmask, gain);
+}
+
+__global__ void k_rbfs_hop_reset(RoundState* st, int t) {
+    st->qcount = 0;
+    st->fcount[t & 1] = 0;
+}
+void launch_rbfs_hop_reset(RoundState* st, int t, hipStream_t s) {
+    hipLaunchKernelGGL(k_rbfs_hop_reset, dim3(1), dim3(1), 0, s, st, t);
+}
+
+__global__ void k_rbfs_expand(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
+                              const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                              const uint8_t* __restrict__ alive, const uint64_t* __restrict__ gain_cur,
+                              uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain_next, int32_t* __restrict__ mark,
+                              int32_t epoch, int32_t* __restrict__ fmark, int32_t fepoch, int32_t* __restrict__ fnext,
+                              int* fnext_count, int32_t* __restrict__ alist, int* aff_fill) {
+    const int nq = *qcount;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int l = lane_id();
+    for (int q = wave; q < nq; q += nwaves) {
+        const int32_t u = qv[q];
+        const int32_t b = qb[q];
+        const int32_t e = min(b + kExpandChunk, rp[u + 1]);
+        const uint64_t g = gain_cur[u];
+        for (int32_t p0 = b; p0 < e; p0 += 64) {
+            const int32_t p = p0 + l;
+            bool want_f = false, want_a = false;
+            int32_t w = 0;
+            if (p < e && g) {
+                w = col[p];
+                if (alive[w]) {
+                    const uint64_t nb = g & ~rmask[w];
+                    if (nb) {
+                        const uint64_t old = atomicOr((unsigned long long*)&rmask[w], (unsigned long long)nb);
+                        const uint64_t nw = nb & ~old;
+                        if (nw) {
+                            atomicOr((unsigned long long*)&gain_next[w], (unsigned long long)nw);
+                            if (fmark[w] != fepoch) want_f = atomicExch(&fmark[w], fepoch) != fepoch;
+                            if (mark[w] != epoch) want_a = atomicExch(&mark[w], epoch) != epoch;
+                        }
+                    }
+                }
+            }
+            const int sf = wave_append_slot(want_f, fnext_count);
+            if (want_f) fnext[sf] = w;
+            const int sa = wave_append_slot(want_a, aff_fill);
+            if (want_a) alist[sa] = w;
+        }
+    }
+}
+void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
+                        const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
+                        int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
+                        int32_t* alist, int* aff_fill, hipStream_t s) {
+    hipLaunchKernelGGL(k_rbfs_expand, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, gain_cur, rmask,
+                       gain_next, mark, epoch, fmark, fepoch, fnext, fnext_count, alist, aff_fill);
+}
+
+__global__ void k_clear_u64_list(const int32_t* __restrict__ list, const int* count, uint64_t* __restrict__ arr) {
+    const int cnt = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) arr[list[i]] = 0ull;
+}
+void launch_clear_u64_list(const int32_t* list, const int* count, uint64_t* arr, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_u64_list, dim3(512), dim3(256), 0, s, list, count, arr);
+}
+
+__global__ void k_decay_masked(const int32_t* __restrict__ alist, RoundState* st, const int* __restrict__ hopfill,
+                               int h, const uint8_t* __restrict__ alive, const int32_t* __restrict__ adeg,
+                               const int32_t* __restrict__ anchor, const uint64_t* __restrict__ rmask,
+                               int64_t* __restrict__ deg, uint8_t* __restrict__ exact) {
+    const int total = st->aff_fill;
+    const int rc = st->rcount;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int32_t v = alist[i];
+        if (!alive[v]) continue;
+        if (h == 1) {
+            deg[v] = adeg[v];
+            exact[v] = 1;
+            continue;
+        }
+        int t = 1;
+        while (t < h && i >= hopfill[t]) ++t;
+        if (t == h && rc <= 64) {
+            // exact values stay exact, bounds stay bounds
+            deg[v] -= (int64_t)__popcll(rmask[v]);
+            continue;
+        }
+        const long long lost = (long long)rc + (h - t >= 1 ? (long long)hopfill[h - t] : 0ll);
+        long long lb = deg[v] - lost;
+        long long ab = adeg[v];
+        int32_t x = v;
+        for (int q = 1; q < h; ++q) {
+            x = anchor[x];
+            if (x < 0 || !alive[x]) break;
+            const long long a = adeg[x];
+            ab = a > ab ? a : ab;
+        }
+        deg[v] = lb > ab ? lb : ab;
+        exact[v] = 0;
+    }
+}
+void launch_decay_masked(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
+                         const int32_t* adeg, const int32_t* anchor, const uint64_t* rmask, int64_t* deg,
+                         uint8_t* exact, hipStream_t s) {
+    hipLaunchKernelGGL(k_decay_masked, dim3(1024), dim3(256), 0, s, alist, st, hopfill, h, alive, adeg, anchor, rmask,
+                       deg, exact);
 }
 
 }  // namespace kh

@@ -563,7 +563,7 @@ void hdeg_sources(kh_graph* g, Planes& PL, const uint8_t* alive, const int32_t* 
         const int64_t rest = count - done;
         const int q = std::min(PL.qmax, pick_q(rest));
         const int ns = (int)std::min<int64_t>(rest, 64ll * q);
-        ms_batch(PL.view(q), g->items, g->n, g->rp, g->col, alive, adeg, src + done, ns, h, deg, st, s);
+        ms_batch(PL.view(q), g->items, g->n, g->rp, g->col, alive, adeg, src + done, ns, nullptr, h, deg, st, s);
         done += ns;
     }
 }
@@ -629,7 +629,9 @@ struct ExactRun {
     int h;
     hipStream_t s;
     Buf<uint8_t> alive, exact;
-    Buf<int32_t> adeg, mark, rlist, alist, qv, qb, srcl, anchor, hopfill;
+    Buf<int32_t> adeg, mark, rlist, alist, qv, qb, srcl, anchor, hopfill, fmark, flA, flB;
+    Buf<uint64_t> rmask, gainA, gainB;
+    int32_t fepoch = 0;
     Buf<int64_t> deg, core, ck, cs, cr;
     Buf<RoundState> st;
     Planes PL;
@@ -663,8 +665,11 @@ struct ExactRun {
     // of R in G[X] (R still alive) into alist, then remove R and update the
     // alive degrees.
     void delete_round(int32_t epoch, const int64_t* key) {
-        const int32_t n = g->n;
-        launch_select(key, alive.p, n, st.p, core.p, rlist.p, mark.p, epoch, 0, s);
+        launch_select(key, alive.p, g->n, st.p, core.p, rlist.p, mark.p, epoch, 0, s);
+        delete_round_tail(epoch);
+    }
+
+    void delete_round_tail(int32_t epoch) {
         launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
         launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 0, alist.p, &st.p->aff_fill,
                       nullptr, s);
@@ -676,6 +681,35 @@ struct ExactRun {
                           &st.p->aff_fill, nullptr, s);
             if (hopfill.p) launch_record_fill(st.p, hopfill.p, t, s);
         }
+        launch_kill_list(rlist.p, &st.p->rcount, alive.p, s);
+        launch_set_int(&st.p->qcount, 0, s);
+        launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
+        launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 1, nullptr, nullptr, adeg.p,
+                      s);
+    }
+
+    // Deletion tail of the lazy peel: mask BFS from R over h hops (R still alive),
+    // remove R, update alive degrees.  Leaves alist/hopfill/rmask for the decay step.
+    void delete_round_masked(int32_t epoch) {
+        launch_rbfs_init(rlist.p, st.p, rmask.p, gainA.p, s);
+        int32_t* fl[2] = {flA.p, flB.p};
+        uint64_t* gain[2] = {gainA.p, gainB.p};
+        for (int t = 1; t <= h; ++t) {
+            if (++fepoch == INT32_MAX) {
+                launch_fill_i32(fmark.p, 0, g->n, s);
+                fepoch = 1;
+            }
+            const int32_t* src = t == 1 ? rlist.p : fl[(t - 1) & 1];
+            const int* srcn = t == 1 ? &st.p->rcount : &st.p->fcount[(t - 1) & 1];
+            launch_rbfs_hop_reset(st.p, t, s);
+            launch_enqueue(src, nullptr, srcn, g->rp, qv.p, qb.p, &st.p->qcount, s);
+            launch_rbfs_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, gain[(t - 1) & 1], rmask.p,
+                               gain[t & 1], mark.p, epoch, fmark.p, fepoch, fl[t & 1], &st.p->fcount[t & 1], alist.p,
+                               &st.p->aff_fill, s);
+            launch_clear_u64_list(src, srcn, gain[(t - 1) & 1], s);
+            launch_record_fill(st.p, hopfill.p, t, s);
+        }
+        launch_clear_u64_list(fl[h & 1], &st.p->fcount[h & 1], gain[h & 1], s);
         launch_kill_list(rlist.p, &st.p->rcount, alive.p, s);
         launch_set_int(&st.p->qcount, 0, s);
         launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
@@ -704,6 +738,16 @@ struct ExactRun {
         exact.alloc(ctx, n);
         anchor.alloc(ctx, n);
         hopfill.alloc(ctx, (size_t)h + 2);
+        fmark.alloc(ctx, n);
+        flA.alloc(ctx, n);
+        flB.alloc(ctx, n);
+        rmask.alloc(ctx, n);
+        gainA.alloc(ctx, n);
+        gainB.alloc(ctx, n);
+        launch_fill_i32(fmark.p, 0, n, s);
+        hip_ok(hipMemsetAsync(rmask.p, 0, 8 * (size_t)n, s));
+        hip_ok(hipMemsetAsync(gainA.p, 0, 8 * (size_t)n, s));
+        hip_ok(hipMemsetAsync(gainB.p, 0, 8 * (size_t)n, s));
         launch_alive_from(nullptr, alive.p, n, s);
         launch_alive_degree(g->rp, g->col, alive.p, adeg.p, n, s);
         launch_fill_i32(mark.p, 0, n, s);
@@ -712,41 +756,39 @@ struct ExactRun {
         launch_lower_bound(nullptr, nullptr, n, h, alive.p, adeg.p, anchor.p, deg.p, exact.p, s);
         int32_t epoch = 0;
         long long iters = 0;
+        const int cap = 64 * PL.qmax;
+        const MsPlanes P = PL.view(PL.qmax);
+        // Each iteration is one fixed kernel sequence: count the inexact vertices
+        // by (bound - c'), then either recompute the smallest bounds (up to 64 Q
+        // sources, at least every one at or below c') or commit the round.  Every
+        // kernel reads the decision from device memory, so the host only checks
+        // for the end every few iterations.
+        const int per_sync = 32;
         for (;;) {
-            if (++iters > 4ll * n + 64) fail(KH_EDEVICE);
-            launch_round_reset(st.p, s);
-            launch_reduce(deg.p, nullptr, alive.p, n, st.p, s);
-            launch_lazy_candidates(alive.p, deg.p, exact.p, n, st.p, srcl.p, 0, 0, s);
+            for (int r = 0; r < per_sync; ++r) {
+                ++epoch;
+                launch_round_reset(st.p, s);
+                launch_reduce(deg.p, nullptr, alive.p, n, st.p, s);
+                launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, s);
+                launch_decide(st.p, cap, s);
+                launch_pick(alive.p, deg.p, exact.p, n, st.p, srcl.p, cap, s);
+                ms_batch(P, g->items, n, g->rp, g->col, alive.p, adeg.p, srcl.p, 0, &st.p->ms_ns, h, deg.p, st.p, s);
+                launch_mark_exact(srcl.p, st.p, exact.p, s);
+                launch_round_begin_gated(st.p, s);
+                launch_select_gated(deg.p, alive.p, n, st.p, core.p, rlist.p, mark.p, epoch, s);
+                delete_round_masked(epoch);
+                launch_anchor(alist.p, &st.p->aff_fill, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 1, s);
+                launch_decay_masked(alist.p, st.p, hopfill.p, h, alive.p, adeg.p, anchor.p, rmask.p, deg.p, exact.p,
+                                    s);
+                launch_clear_u64_list(alist.p, &st.p->aff_fill, rmask.p, s);
+                launch_clear_u64_list(rlist.p, &st.p->rcount, rmask.p, s);
+            }
+            iters += per_sync;
             read_state(ctx, st.p, s);
-            RoundState hs = *ctx->host_state;
-            if (hs.alive_count == 0) break;
-            if (hs.rc_count > 0) {
-                // fill the batch with vertices whose bound is just above c: they are the
-                // next ones to need an exact value, and a sweep costs the same for 1 or
-                // 64 Q sources
-                const int cap = 64 * PL.qmax;
-                int total = hs.rc_count;
-                if (total % cap) {
-                    launch_lazy_candidates(alive.p, deg.p, exact.p, n, st.p, srcl.p, 1,
-                                           (total / cap + 1) * cap, s);
-                    read_state(ctx, st.p, s);
-                    hs = *ctx->host_state;
-                    total += std::min(hs.opt_count, (total / cap + 1) * cap - total);
-                }
-                hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, total, h, deg.p, st.p, s);
-                launch_set_flags(srcl.p, total, exact.p, 1, s);
-                recomputed += total;
-                continue;
-            }
-            ++epoch;
-            launch_round_begin(st.p, nullptr, nullptr, nullptr, 0, s);
-            delete_round(epoch, deg.p);
-            launch_anchor(alist.p, &st.p->aff_fill, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 1, s);
-            launch_decay_bound(alist.p, st.p, hopfill.p, h, alive.p, adeg.p, anchor.p, deg.p, exact.p, s);
-            if (trace_on()) {
-                read_state(ctx, st.p, s);
-                trace_round(*ctx->host_state, "lazy", t0);
-            }
+            const RoundState hs = *ctx->host_state;
+            if (hs.mode == 2) break;
+            if (iters > 4ll * n + 4096) fail(KH_EDEVICE);
+            trace_round(hs, "lazy", t0);
         }
         fin = *ctx->host_state;
         prof_add_counters(ctx, fin);
@@ -833,7 +875,7 @@ struct SampledRun {
     bool early_stop = false;
     hipStream_t s;
     Buf<uint8_t> alive, rank;
-    Buf<int32_t> mark, rlist, wl, rc, lostmax, chA, chB, qv, qb, cursor;
+    Buf<int32_t> mark, rlist, wl, rc, lostmax, chA, chB, qv, qb, cursor, order;
     Buf<int64_t> d, core, ck, cs, cr, partials;
     Buf<RoundState> st;
     Lists L;
@@ -856,6 +898,7 @@ struct SampledRun {
         qv.alloc(ctx, qcap);
         qb.alloc(ctx, qcap);
         cursor.alloc(ctx, (size_t)std::max<int64_t>(g->nnz, 1));
+        order.alloc(ctx, (size_t)std::max<int64_t>(g->nnz, 1));
         d.alloc(ctx, n);
         core.alloc(ctx, n);
         ck.alloc(ctx, (size_t)n + 1);
@@ -910,7 +953,7 @@ struct SampledRun {
         launch_union1(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.view(1), nullptr, nullptr, st.p, s);
         for (int i = 2; i <= h; ++i)
             launch_union(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2, L.view(i - 1),
-                         L.view(i), cursor.p, nullptr, nullptr, st.p, s);
+                         L.view(i), cursor.p, order.p, nullptr, nullptr, st.p, s);
         launch_estimate(nullptr, nullptr, n, alive.p, rank.p, L.size[h].p, L.kk[h].p, M, d.p, st.p, s);
     }
 
@@ -959,7 +1002,8 @@ struct SampledRun {
                                       changed[1], &st.p->changed_count[1], st.p, s);
                     else
                         launch_union(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2,
-                                     L.view(i - 1), L.view(i), cursor.p, changed[i & 1], &st.p->changed_count[i & 1],
+                                     L.view(i - 1), L.view(i), cursor.p, order.p, changed[i & 1],
+                                     &st.p->changed_count[i & 1],
                                      st.p, s);
                 }
                 launch_estimate(changed[h & 1], &st.p->changed_count[h & 1], n, alive.p, rank.p, L.size[h].p,

@@ -22,6 +22,8 @@ constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 // Threads of a union work-group and the largest hash table (entries) that fits
 // the LDS budget of one work-group.
 constexpr int kUnionThreads = 256;
+// Vertices with more neighbours than this order their arcs by list head rank in the union.
+constexpr int kHubDegree = 1024;
 constexpr int kMaxHashLog2 = 14;  // 16384 entries = 64 KiB
 
 // Largest integer M the sampled path accepts: the per-vertex LDS hash table
@@ -45,6 +47,11 @@ struct RoundState {
     int changed_count[2];    // vertices whose (k, B) changed (ping-pong by level parity)
     int rc_count;            // worklist vertices that must be re-merged / recomputed
     int opt_count;           // optional recomputations appended to a batch
+    int mode;                // device-driven exact peel: 0 commit, 1 recompute, 2 done
+    int ms_ns;               // sources of the current device-driven h-degree batch
+    long long hi;            // recompute every inexact vertex whose bound is <= hi
+    int hist[48];            // inexact vertices by bound - c: [0] <= 0, [b] in [2^(b-1), 2^b)
+    int fcount[2];           // R-mask BFS frontier fills (ping-pong by hop parity)
     int overflow;            // an estimate exceeded the representable range
     unsigned long long te;     // edges traversed (exact h-degree work)
     unsigned long long arcs;   // adjacency entries read by the h-degree kernels
@@ -114,6 +121,29 @@ void launch_record_fill(RoundState* st, int* hopfill, int t, hipStream_t s);
 void launch_lazy_candidates(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
                             int32_t* out, int pass, int opt_cap, hipStream_t s);
 void launch_set_flags(const int32_t* list, int count, uint8_t* flags, uint8_t v, hipStream_t s);
+// device-driven exact peel steps
+void launch_bound_hist(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
+                       hipStream_t s);
+void launch_decide(RoundState* st, int cap, hipStream_t s);
+void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
+                 int32_t* out, int cap, hipStream_t s);
+void launch_mark_exact(const int32_t* list, RoundState* st, uint8_t* exact, hipStream_t s);
+void launch_round_begin_gated(RoundState* st, hipStream_t s);
+// R-mask BFS: after h hops rmask[v] holds bit (j mod 64) for every deleted r_j within
+// distance h of v in G[X]; first-visited vertices are appended to alist in hop order.
+void launch_rbfs_init(const int32_t* rlist, RoundState* st, uint64_t* rmask, uint64_t* gain, hipStream_t s);
+void launch_rbfs_hop_reset(RoundState* st, int t, hipStream_t s);
+void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
+                        const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
+                        int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
+                        int32_t* alist, int* aff_fill, hipStream_t s);
+void launch_clear_u64_list(const int32_t* list, const int* count, uint64_t* arr, hipStream_t s);
+// exact decrement for vertices at distance exactly h (deg -= |R within h|), bound otherwise
+void launch_decay_masked(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
+                         const int32_t* adeg, const int32_t* anchor, const uint64_t* rmask, int64_t* deg,
+                         uint8_t* exact, hipStream_t s);
+void launch_select_gated(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core, int32_t* rlist,
+                         int32_t* mark, int32_t epoch, hipStream_t s);
 
 // ---- kernels: bit-parallel multi-source bounded BFS (kh_msbfs.hip) ---------------------
 
@@ -143,10 +173,11 @@ struct MsItems {
     int32_t* split_list;  // vertices with several items
 };
 
-// One batch of ns <= 64 Q sources: deg[src[j]] = |N(src[j]; h, X)| - 1.
+// One batch of ns <= 64 Q sources: deg[src[j]] = |N(src[j]; h, X)| - 1.  With
+// ns_dev != NULL the batch size is min(*ns_dev, 64 Q), read on the device (0: no-op).
 void ms_batch(const MsPlanes& P, const MsItems& I, int32_t n, const int32_t* rp, const int32_t* col,
-              const uint8_t* alive, const int32_t* adeg, const int32_t* src, int ns, int h, int64_t* deg,
-              RoundState* st, hipStream_t s);
+              const uint8_t* alive, const int32_t* adeg, const int32_t* src, int ns, const int* ns_dev, int h,
+              int64_t* deg, RoundState* st, hipStream_t s);
 
 // ---- kernels: sampled lists (kh_union.hip) ---------------------------------------------
 
@@ -172,7 +203,8 @@ void launch_union1(const int32_t* worklist, const int* wl_count, int32_t n, cons
 // Level i >= 2.
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
                   const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, LevelView prev, LevelView cur,
-                  int32_t* cursor, int32_t* changed, int* changed_count, RoundState* st, hipStream_t s);
+                  int32_t* cursor, int32_t* order, int32_t* changed, int* changed_count, RoundState* st,
+                  hipStream_t s);
 // Propagate the deletions and changes of level i-1 over the arcs of the queued
 // vertices: mark + append alive neighbours, fold the highest lost rank into
 // lostmax[], and keep m[.,i] current.

@@ -21,8 +21,9 @@
 namespace kh {
 
 template <int Q>
-__global__ void k_ms_init(const int32_t* __restrict__ src, int ns, uint64_t* __restrict__ vis,
+__global__ void k_ms_init(const int32_t* __restrict__ src, int ns, const int* ns_dev, uint64_t* __restrict__ vis,
                           const int32_t* __restrict__ adeg, uint64_t* __restrict__ valid, RoundState* st) {
+    if (ns_dev) ns = min(*ns_dev, 64 * Q);
     unsigned long long te = 0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ns; j += gridDim.x * blockDim.x) {
         const int32_t s = src[j];
@@ -39,10 +40,11 @@ __global__ void k_ms_init(const int32_t* __restrict__ src, int ns, uint64_t* __r
 
 // Hop 1: push the sources' bits to their alive neighbours.
 template <int Q>
-__global__ void k_ms_push(const int32_t* __restrict__ src, int ns, const int32_t* __restrict__ rp,
+__global__ void k_ms_push(const int32_t* __restrict__ src, int ns, const int* ns_dev, const int32_t* __restrict__ rp,
                           const int32_t* __restrict__ col, const uint8_t* __restrict__ alive,
                           uint64_t* __restrict__ acc, uint32_t* __restrict__ bmT, int32_t* __restrict__ touched,
                           int* tcount, RoundState* st) {
+    if (ns_dev) ns = min(*ns_dev, 64 * Q);
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int l = lane_id();
@@ -119,7 +121,9 @@ __global__ __launch_bounds__(256) void k_ms_pull(int32_t nitems, const int32_t* 
                                                  const uint32_t* __restrict__ bm_cur, uint64_t* __restrict__ fr_next,
                                                  uint32_t* __restrict__ bm_next, uint64_t* __restrict__ acc,
                                                  const uint64_t* __restrict__ valid, int last,
-                                                 const int32_t* __restrict__ adeg, RoundState* st) {
+                                                 const int32_t* __restrict__ adeg, RoundState* st,
+                                                 const int* ns_dev) {
+    if (ns_dev && *ns_dev == 0) return;
     const int l = lane_id();
     const int j = l % Q;
     const int gbase = l - j;
@@ -248,7 +252,8 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x, int l) {
 }
 
 template <int Q>
-__global__ void k_ms_count(int32_t n, uint64_t* __restrict__ vis, uint32_t* __restrict__ cnt) {
+__global__ void k_ms_count(int32_t n, uint64_t* __restrict__ vis, uint32_t* __restrict__ cnt, const int* ns_dev) {
+    if (ns_dev && *ns_dev == 0) return;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int l = lane_id();
@@ -279,8 +284,9 @@ __global__ void k_ms_count(int32_t n, uint64_t* __restrict__ vis, uint32_t* __re
         if (c[q]) atomicAdd(&cnt[q * 64 + l], c[q]);
 }
 
-__global__ void k_ms_scatter(const int32_t* __restrict__ src, int ns, uint32_t* __restrict__ cnt,
-                             int64_t* __restrict__ deg) {
+__global__ void k_ms_scatter(const int32_t* __restrict__ src, int ns, const int* ns_dev, int qmax,
+                             uint32_t* __restrict__ cnt, int64_t* __restrict__ deg) {
+    if (ns_dev) ns = min(*ns_dev, 64 * qmax);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ns; j += gridDim.x * blockDim.x) {
         deg[src[j]] = (int64_t)cnt[j] - 1;
         cnt[j] = 0u;
@@ -289,15 +295,17 @@ __global__ void k_ms_scatter(const int32_t* __restrict__ src, int ns, uint32_t* 
 
 template <int Q>
 static void ms_batch_q(const MsPlanes& P, const MsItems& I, int32_t n, const int32_t* rp, const int32_t* col,
-                       const uint8_t* alive, const int32_t* adeg, const int32_t* src, int ns, int h, int64_t* deg,
-                       RoundState* st, hipStream_t s) {
+                       const uint8_t* alive, const int32_t* adeg, const int32_t* src, int ns, const int* ns_dev, int h,
+                       int64_t* deg, RoundState* st, hipStream_t s) {
     const int64_t bmwords = ((int64_t)n + 31) / 32;
-    hipLaunchKernelGGL(k_ms_init<Q>, dim3(grid_for(ns, 256, 64)), dim3(256), 0, s, src, ns, P.vis, adeg, P.valid, st);
+    const int nsg = ns_dev ? 64 * Q : ns;  // grid sizing
+    hipLaunchKernelGGL(k_ms_init<Q>, dim3(grid_for(nsg, 256, 64)), dim3(256), 0, s, src, ns, ns_dev, P.vis, adeg,
+                       P.valid, st);
     // hop 1: push
     launch_fill_u32(P.bmT, 0u, bmwords, s);
     launch_set_int(P.touched_count, 0, s);
-    hipLaunchKernelGGL(k_ms_push<Q>, dim3(grid_for((int64_t)ns * 64, 256, 4096)), dim3(256), 0, s, src, ns, rp, col,
-                       alive, P.acc, P.bmT, P.touched, P.touched_count, st);
+    hipLaunchKernelGGL(k_ms_push<Q>, dim3(grid_for((int64_t)nsg * 64, 256, 4096)), dim3(256), 0, s, src, ns, ns_dev,
+                       rp, col, alive, P.acc, P.bmT, P.touched, P.touched_count, st);
     uint64_t* fr_cur = P.frA;
     uint32_t* bm_cur = P.bmA;
     uint64_t* fr_nxt = P.frB;
@@ -316,7 +324,7 @@ static void ms_batch_q(const MsPlanes& P, const MsItems& I, int32_t n, const int
         const bool timed = T && T->used < T->cap;
         if (timed) (void)hipEventRecord(T->ev[2 * T->used], s);
         hipLaunchKernelGGL(k_ms_pull<Q>, dim3(pull_grid), dim3(256), 0, s, I.nitems, I.u, I.beg, I.end, I.split, col,
-                           alive, P.vis, fr_cur, bm_cur, fr_nxt, bm_nxt, P.acc, P.valid, last, adeg, st);
+                           alive, P.vis, fr_cur, bm_cur, fr_nxt, bm_nxt, P.acc, P.valid, last, adeg, st, ns_dev);
         if (timed) {
             (void)hipEventRecord(T->ev[2 * T->used + 1], s);
             T->used += 1;
@@ -326,20 +334,20 @@ static void ms_batch_q(const MsPlanes& P, const MsItems& I, int32_t n, const int
                                I.split_list, (const int*)nullptr, I.nsplit, P.acc, P.vis, fr_nxt, bm_nxt, P.valid,
                                last, adeg, st);
     }
-    hipLaunchKernelGGL(k_ms_count<Q>, dim3(grid_for((int64_t)n, 256, 4096)), dim3(256), 0, s, n, P.vis, P.cnt);
-    hipLaunchKernelGGL(k_ms_scatter, dim3(grid_for(ns, 256, 64)), dim3(256), 0, s, src, ns, P.cnt, deg);
+    hipLaunchKernelGGL(k_ms_count<Q>, dim3(grid_for((int64_t)n, 256, 4096)), dim3(256), 0, s, n, P.vis, P.cnt, ns_dev);
+    hipLaunchKernelGGL(k_ms_scatter, dim3(grid_for(nsg, 256, 64)), dim3(256), 0, s, src, ns, ns_dev, Q, P.cnt, deg);
 }
 
 void ms_batch(const MsPlanes& P, const MsItems& I, int32_t n, const int32_t* rp, const int32_t* col,
-              const uint8_t* alive, const int32_t* adeg, const int32_t* src, int ns, int h, int64_t* deg,
-              RoundState* st, hipStream_t s) {
-    if (ns <= 0 || n <= 0) return;
+              const uint8_t* alive, const int32_t* adeg, const int32_t* src, int ns, const int* ns_dev, int h,
+              int64_t* deg, RoundState* st, hipStream_t s) {
+    if ((!ns_dev && ns <= 0) || n <= 0) return;
     switch (P.Q) {
-        case 1: ms_batch_q<1>(P, I, n, rp, col, alive, adeg, src, ns, h, deg, st, s); break;
-        case 2: ms_batch_q<2>(P, I, n, rp, col, alive, adeg, src, ns, h, deg, st, s); break;
-        case 4: ms_batch_q<4>(P, I, n, rp, col, alive, adeg, src, ns, h, deg, st, s); break;
-        case 8: ms_batch_q<8>(P, I, n, rp, col, alive, adeg, src, ns, h, deg, st, s); break;
-        default: ms_batch_q<16>(P, I, n, rp, col, alive, adeg, src, ns, h, deg, st, s); break;
+        case 1: ms_batch_q<1>(P, I, n, rp, col, alive, adeg, src, ns, ns_dev, h, deg, st, s); break;
+        case 2: ms_batch_q<2>(P, I, n, rp, col, alive, adeg, src, ns, ns_dev, h, deg, st, s); break;
+        case 4: ms_batch_q<4>(P, I, n, rp, col, alive, adeg, src, ns, ns_dev, h, deg, st, s); break;
+        case 8: ms_batch_q<8>(P, I, n, rp, col, alive, adeg, src, ns, ns_dev, h, deg, st, s); break;
+        default: ms_batch_q<16>(P, I, n, rp, col, alive, adeg, src, ns, ns_dev, h, deg, st, s); break;
     }
 }
 

@@ -205,11 +205,13 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
                                                const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
                                                int32_t M, int hash_log2, LevelView prev, LevelView cur,
-                                               int32_t* __restrict__ cursor, int32_t* __restrict__ changed,
-                                               int* changed_count, RoundState* st) {
+                                               int32_t* __restrict__ cursor, int32_t* __restrict__ order,
+                                               int32_t* __restrict__ changed, int* changed_count, RoundState* st) {
     extern __shared__ uint32_t tab[];
     __shared__ int hist[256];
     __shared__ int hk[256];
+    __shared__ int hh[256];   // hubs: neighbours by head rank, then scatter cursors
+    __shared__ int hcum[257];  // hubs: neighbours whose list head rank is >= L
     __shared__ int s_kmax, s_htop, s_count, s_k, s_size, s_ok, s_os, s_lost;
     const int tid = threadIdx.x;
     const int bs = blockDim.x;
@@ -221,9 +223,13 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
         const int32_t v = worklist ? worklist[wi] : wi;
         if (!alive[v]) continue;
         const int32_t b = rp[v], e = rp[v + 1];
+        // hubs: order the arcs by the head rank of the neighbour's list so that
+        // level L only visits the neighbours whose list reaches rank L
+        const bool hub = (e - b) > kHubDegree;
         for (int t = tid; t < hcap; t += bs) tab[t] = kEmptyKey;
         hist[tid] = 0;
         hk[tid] = 0;
+        hh[tid] = 0;
         if (tid == 0) {
             s_kmax = 0;
             s_htop = rank[v];
@@ -244,6 +250,7 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
                 if (prev.size[w] > 0) {
                     const int hr = key_rank(prev.keys[prev.off[w]]);
                     htop_l = hr > htop_l ? hr : htop_l;
+                    if (hub) atomicAdd(&hh[hr], 1);
                 }
             }
         }
@@ -254,10 +261,33 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             atomicMax(&s_htop, htop_l);
         }
         __syncthreads();
+        if (hub) {
+            if (tid == 0) {
+                int run = 0;
+                hcum[256] = 0;
+                for (int r = 255; r >= 0; --r) {
+                    const int c = hh[r];
+                    hh[r] = run;  // scatter cursor of head rank r
+                    run += c;
+                    hcum[r] = run;
+                }
+            }
+            __syncthreads();
+            for (int32_t p = b + tid; p < e; p += bs) {
+                const int32_t w = col[p];
+                if (alive[w] && prev.size[w] > 0) {
+                    const int hr = key_rank(prev.keys[prev.off[w]]);
+                    order[b + atomicAdd(&hh[hr], 1)] = p;
+                }
+            }
+            __syncthreads();
+        }
         const int kmax = s_kmax;
         int k = kmax;
         for (int L = s_htop; L >= kmax; --L) {
-            for (int32_t p = b + tid; p < e; p += bs) {
+            const int32_t span = hub ? hcum[L] : e - b;
+            for (int32_t i = tid; i < span; i += bs) {
+                const int32_t p = hub ? order[b + i] : b + i;
                 const int32_t w = col[p];
                 if (!alive[w]) continue;
                 int c = cursor[p];
@@ -337,7 +367,8 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
 
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
                   const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, LevelView prev, LevelView cur,
-                  int32_t* cursor, int32_t* changed, int* changed_count, RoundState* st, hipStream_t s) {
+                  int32_t* cursor, int32_t* order, int32_t* changed, int* changed_count, RoundState* st,
+                  hipStream_t s) {
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
     const size_t lds = sizeof(uint32_t) << hash_log2;
@@ -347,7 +378,7 @@ void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const
         lds_set = lds;
     }
     hipLaunchKernelGGL(k_union, dim3(grid), dim3(kUnionThreads), lds, s, worklist, wl_count, n, rp, col, alive, rank,
-                       M, hash_log2, prev, cur, cursor, changed, changed_count, st);
+                       M, hash_log2, prev, cur, cursor, order, changed, changed_count, st);
 }
 
 // ---- propagation of deletions and changes to the next level ---------------------------------
