@@ -170,18 +170,21 @@ kh_status kh_dense(kh_graph *g, const kh_params *params, const int32_t *core_in,
 
 /* ---- measurement hooks ------------------------------------------------------ */
 
-/* Start (on != 0; resets the totals) or stop recording the h-degree pull
- * kernel: every launch is bracketed by HIP events on the stream it runs on,
- * and the kernel counts the bytes it must move (work items, adjacency ids,
- * visited/frontier words read and written) and, separately, the neighbour
- * frontier words it gathers. */
+/* Start (on != 0; resets the totals) or stop recording two kernels: the
+ * h-degree pull kernel (kernel 0) and the sample-list union (kernel 1).  Every
+ * launch is bracketed by HIP events on the stream it runs on (the round loops
+ * then launch directly instead of replaying captured graphs), and the kernels
+ * count the bytes they must move: for the pull kernel work items, adjacency
+ * ids and visited/frontier words read and written, plus (separately) the
+ * neighbour frontier words it gathers; for the union the adjacency metadata,
+ * the list entries read and the list written. */
 kh_status kh_profile_enable(kh_context *ctx, int32_t on);
 
-/* Totals since kh_profile_enable(ctx, 1): launches, summed kernel time (ms),
- * algorithmic bytes without gathers, and gathered bytes.  Any pointer may be
- * NULL.  Synchronises the recorded events. */
-kh_status kh_profile_read(kh_context *ctx, int64_t *launches, double *total_ms, int64_t *alg_bytes,
-                          int64_t *gather_bytes);
+/* Totals for `kernel` (0 or 1) since kh_profile_enable(ctx, 1): launches,
+ * summed kernel time (ms), algorithmic bytes, and gathered bytes (kernel 0
+ * only).  Any output pointer may be NULL.  Synchronises the recorded events. */
+kh_status kh_profile_read(kh_context *ctx, int32_t kernel, int64_t *launches, double *total_ms,
+                          int64_t *alg_bytes, int64_t *gather_bytes);
 
 #ifdef __cplusplus
 }

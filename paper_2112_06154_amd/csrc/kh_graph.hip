@@ -178,6 +178,7 @@ __global__ void k_round_reset(RoundState* st) {
     for (int b = 0; b < 48; ++b) st->hist[b] = 0;
     st->fcount[0] = 0;
     st->fcount[1] = 0;
+    st->epoch += 1;
 }
 void launch_round_reset(RoundState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, s, st);
@@ -370,6 +371,7 @@ void launch_next_frontier(RoundState* st, hipStream_t s) {
 }
 
 __global__ void k_level_reset(RoundState* st, int level) {
+    st->epoch += 1;
     st->qcount = 0;
     st->wl_count = 0;
     st->rc_count = 0;
@@ -733,6 +735,7 @@ __global__ void k_select_gated(const int64_t* __restrict__ key, uint8_t* __restr
                                int64_t* __restrict__ core, int32_t* __restrict__ rlist, int32_t* __restrict__ mark,
                                int32_t epoch) {
     if (st->mode != 0) return;
+    if (epoch < 0) epoch = st->epoch;
     const long long c = st->c;
     const int32_t stride = gridDim.x * blockDim.x;
     for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
@@ -773,6 +776,7 @@ void launch_rbfs_init(const int32_t* rlist, RoundState* st, uint64_t* rmask, uin
 }
 
 __global__ void k_rbfs_hop_reset(RoundState* st, int t) {
+    st->fepoch += 1;
     st->qcount = 0;
     st->fcount[t & 1] = 0;
 }
@@ -785,7 +789,9 @@ __global__ void k_rbfs_expand(const int32_t* __restrict__ qv, const int32_t* __r
                               const uint8_t* __restrict__ alive, const uint64_t* __restrict__ gain_cur,
                               uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain_next, int32_t* __restrict__ mark,
                               int32_t epoch, int32_t* __restrict__ fmark, int32_t fepoch, int32_t* __restrict__ fnext,
-                              int* fnext_count, int32_t* __restrict__ alist, int* aff_fill) {
+                              int* fnext_count, int32_t* __restrict__ alist, int* aff_fill, RoundState* st) {
+    if (epoch < 0) epoch = st->epoch;
+    if (fepoch < 0) fepoch = st->fepoch;
     const int nq = *qcount;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -824,9 +830,9 @@ __global__ void k_rbfs_expand(const int32_t* __restrict__ qv, const int32_t* __r
 void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
                         const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
                         int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
-                        int32_t* alist, int* aff_fill, hipStream_t s) {
+                        int32_t* alist, int* aff_fill, RoundState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_rbfs_expand, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, gain_cur, rmask,
-                       gain_next, mark, epoch, fmark, fepoch, fnext, fnext_count, alist, aff_fill);
+                       gain_next, mark, epoch, fmark, fepoch, fnext, fnext_count, alist, aff_fill, st);
 }
 
 __global__ void k_clear_u64_list(const int32_t* __restrict__ list, const int* count, uint64_t* __restrict__ arr) {

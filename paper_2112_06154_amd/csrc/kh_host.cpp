@@ -66,10 +66,10 @@ struct kh_context {
     RoundState* host_state = nullptr;  // pinned mirror of the device round state
     // pull-kernel timing (kh_profile_enable / kh_profile_read)
     bool prof_on = false;
-    PullTimer timer;
-    long long prof_launches = 0;
-    double prof_ms = 0.0;
-    unsigned long long prof_bytes = 0, prof_gather = 0;
+    PullTimer timer[2];  // 0: h-degree pull, 1: sample-list union
+    long long prof_launches[2] = {0, 0};
+    double prof_ms[2] = {0.0, 0.0};
+    unsigned long long prof_bytes[2] = {0, 0}, prof_gather = 0;
 };
 
 namespace {
@@ -227,33 +227,38 @@ extern "C" kh_status kh_context_create(int32_t device, uint64_t hbm_budget_bytes
 extern "C" void kh_context_destroy(kh_context* ctx) {
     if (!ctx) return;
     if (ctx->host_state) (void)hipHostFree(ctx->host_state);
-    if (ctx->timer.ev) {
-        for (int i = 0; i < 2 * ctx->timer.cap; ++i) (void)hipEventDestroy(ctx->timer.ev[i]);
-        delete[] ctx->timer.ev;
+    for (auto& T : ctx->timer) {
+        if (T.ev) {
+            for (int i = 0; i < 2 * T.cap; ++i) (void)hipEventDestroy(T.ev[i]);
+            delete[] T.ev;
+        }
     }
     delete ctx;
 }
 
 namespace {
 
-// Fold the recorded pull launches into the context totals.
+// Fold the recorded launches into the context totals.
 void prof_collect(kh_context* ctx) {
-    PullTimer& T = ctx->timer;
-    for (int i = 0; i < T.used; ++i) {
-        float ms = 0.f;
-        hip_ok(hipEventSynchronize(T.ev[2 * i + 1]));
-        hip_ok(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
-        ctx->prof_ms += ms;
-        ctx->prof_launches += 1;
+    for (int k = 0; k < 2; ++k) {
+        PullTimer& T = ctx->timer[k];
+        for (int i = 0; i < T.used; ++i) {
+            float ms = 0.f;
+            hip_ok(hipEventSynchronize(T.ev[2 * i + 1]));
+            hip_ok(hipEventElapsedTime(&ms, T.ev[2 * i], T.ev[2 * i + 1]));
+            ctx->prof_ms[k] += ms;
+            ctx->prof_launches[k] += 1;
+        }
+        T.used = 0;
     }
-    T.used = 0;
 }
 
 void prof_add_counters(kh_context* ctx, const RoundState& hs) {
     if (!ctx->prof_on) return;
     prof_collect(ctx);
-    ctx->prof_bytes += hs.pull_bytes;
+    ctx->prof_bytes[0] += hs.pull_bytes;
     ctx->prof_gather += hs.pull_gather;
+    ctx->prof_bytes[1] += hs.union_bytes;
 }
 
 }  // namespace
@@ -262,19 +267,23 @@ extern "C" kh_status kh_profile_enable(kh_context* ctx, int32_t on) {
     if (!ctx) return KH_EINVAL;
     try {
         hip_ok(hipSetDevice(ctx->device));
-        if (on && !ctx->timer.ev) {
-            const int cap = 8192;
-            ctx->timer.ev = new hipEvent_t[2 * cap];
-            for (int i = 0; i < 2 * cap; ++i) hip_ok(hipEventCreate(&ctx->timer.ev[i]));
-            ctx->timer.cap = cap;
+        for (auto& T : ctx->timer) {
+            if (on && !T.ev) {
+                const int cap = 8192;
+                T.ev = new hipEvent_t[2 * cap];
+                for (int i = 0; i < 2 * cap; ++i) hip_ok(hipEventCreate(&T.ev[i]));
+                T.cap = cap;
+            }
         }
         if (ctx->prof_on) prof_collect(ctx);
-        ctx->timer.used = 0;
         ctx->prof_on = on != 0;
         if (on) {
-            ctx->prof_launches = 0;
-            ctx->prof_ms = 0.0;
-            ctx->prof_bytes = 0;
+            for (int k = 0; k < 2; ++k) {
+                ctx->timer[k].used = 0;
+                ctx->prof_launches[k] = 0;
+                ctx->prof_ms[k] = 0.0;
+                ctx->prof_bytes[k] = 0;
+            }
             ctx->prof_gather = 0;
         }
     } catch (const KhError& e) {
@@ -283,18 +292,18 @@ extern "C" kh_status kh_profile_enable(kh_context* ctx, int32_t on) {
     return KH_OK;
 }
 
-extern "C" kh_status kh_profile_read(kh_context* ctx, int64_t* launches, double* total_ms, int64_t* alg_bytes,
-                                     int64_t* gather_bytes) {
-    if (!ctx) return KH_EINVAL;
+extern "C" kh_status kh_profile_read(kh_context* ctx, int32_t kernel, int64_t* launches, double* total_ms,
+                                     int64_t* alg_bytes, int64_t* gather_bytes) {
+    if (!ctx || kernel < 0 || kernel > 1) return KH_EINVAL;
     try {
         if (ctx->prof_on) prof_collect(ctx);
     } catch (const KhError& e) {
         return e.code;
     }
-    if (launches) *launches = ctx->prof_launches;
-    if (total_ms) *total_ms = ctx->prof_ms;
-    if (alg_bytes) *alg_bytes = (int64_t)ctx->prof_bytes;
-    if (gather_bytes) *gather_bytes = (int64_t)ctx->prof_gather;
+    if (launches) *launches = ctx->prof_launches[kernel];
+    if (total_ms) *total_ms = ctx->prof_ms[kernel];
+    if (alg_bytes) *alg_bytes = (int64_t)ctx->prof_bytes[kernel];
+    if (gather_bytes) *gather_bytes = kernel == 0 ? (int64_t)ctx->prof_gather : 0;
     return KH_OK;
 }
 
@@ -557,7 +566,7 @@ void hdeg_sources(kh_graph* g, Planes& PL, const uint8_t* alive, const int32_t* 
                   int h, int64_t* deg, RoundState* st, hipStream_t s) {
     int64_t done = 0;
     kh_context* ctx = g->ctx;
-    PL.timer = ctx->prof_on ? &ctx->timer : nullptr;
+    PL.timer = ctx->prof_on ? &ctx->timer[0] : nullptr;
     while (done < count) {
         if (PL.timer && PL.timer->used + 8 >= PL.timer->cap) prof_collect(ctx);
         const int64_t rest = count - done;
@@ -584,6 +593,50 @@ void init_state(RoundState* st, hipStream_t s) {
 
 struct Candidates {
     std::vector<int64_t> k, size, sum;
+};
+
+bool graphs_off() {
+    const char* e = std::getenv("KH_NO_GRAPH");
+    return e && e[0] && e[0] != '0';
+}
+
+// Replays a fixed sequence of kernel launches (recorded once by stream capture)
+// on a private stream that is ordered after the caller's stream.  The sequences
+// hold kernels only (clears are fill kernels), and every launch reads its
+// round-dependent values from device memory, so each replay is the same work as
+// issuing the launches directly.
+struct Replay {
+    hipStream_t gs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool direct = false;
+    ~Replay() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (gs) (void)hipStreamDestroy(gs);
+    }
+    template <typename F>
+    hipStream_t prepare(hipStream_t caller, bool use_graph, F&& record) {
+        hip_ok(hipStreamCreate(&gs));
+        hipEvent_t ev;
+        hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        hip_ok(hipEventRecord(ev, caller));
+        hip_ok(hipStreamWaitEvent(gs, ev, 0));
+        hip_ok(hipEventDestroy(ev));
+        direct = !use_graph;
+        if (!direct) {
+            hip_ok(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+            record(gs);
+            hip_ok(hipStreamEndCapture(gs, &graph));
+            hip_ok(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        }
+        return gs;
+    }
+    template <typename F>
+    void run(F&& record) {
+        if (direct) record(gs);
+        else hip_ok(hipGraphLaunch(exec, gs));
+    }
 };
 
 void pick_dense(const Candidates& C, bool prune, double eps, int64_t maxcore, kh_result* res) {
@@ -631,7 +684,6 @@ struct ExactRun {
     Buf<uint8_t> alive, exact;
     Buf<int32_t> adeg, mark, rlist, alist, qv, qb, srcl, anchor, hopfill, fmark, flA, flB;
     Buf<uint64_t> rmask, gainA, gainB;
-    int32_t fepoch = 0;
     Buf<int64_t> deg, core, ck, cs, cr;
     Buf<RoundState> st;
     Planes PL;
@@ -695,17 +747,13 @@ struct ExactRun {
         int32_t* fl[2] = {flA.p, flB.p};
         uint64_t* gain[2] = {gainA.p, gainB.p};
         for (int t = 1; t <= h; ++t) {
-            if (++fepoch == INT32_MAX) {
-                launch_fill_i32(fmark.p, 0, g->n, s);
-                fepoch = 1;
-            }
             const int32_t* src = t == 1 ? rlist.p : fl[(t - 1) & 1];
             const int* srcn = t == 1 ? &st.p->rcount : &st.p->fcount[(t - 1) & 1];
             launch_rbfs_hop_reset(st.p, t, s);
             launch_enqueue(src, nullptr, srcn, g->rp, qv.p, qb.p, &st.p->qcount, s);
             launch_rbfs_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, gain[(t - 1) & 1], rmask.p,
-                               gain[t & 1], mark.p, epoch, fmark.p, fepoch, fl[t & 1], &st.p->fcount[t & 1], alist.p,
-                               &st.p->aff_fill, s);
+                               gain[t & 1], mark.p, epoch, fmark.p, -1, fl[t & 1], &st.p->fcount[t & 1], alist.p,
+                               &st.p->aff_fill, st.p, s);
             launch_clear_u64_list(src, srcn, gain[(t - 1) & 1], s);
             launch_record_fill(st.p, hopfill.p, t, s);
         }
@@ -713,8 +761,7 @@ struct ExactRun {
         launch_kill_list(rlist.p, &st.p->rcount, alive.p, s);
         launch_set_int(&st.p->qcount, 0, s);
         launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
-        launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, epoch, 1, nullptr, nullptr, adeg.p,
-                      s);
+        launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, 0, 1, nullptr, nullptr, adeg.p, s);
     }
 
     void trace_round(const RoundState& hs, const char* what, Clock::time_point t0) {
@@ -754,19 +801,21 @@ struct ExactRun {
         launch_fill_i64(core.p, -1, n, s);
         launch_anchor(nullptr, nullptr, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 0, s);
         launch_lower_bound(nullptr, nullptr, n, h, alive.p, adeg.p, anchor.p, deg.p, exact.p, s);
-        int32_t epoch = 0;
         long long iters = 0;
         const int cap = 64 * PL.qmax;
-        const MsPlanes P = PL.view(PL.qmax);
         // Each iteration is one fixed kernel sequence: count the inexact vertices
         // by (bound - c'), then either recompute the smallest bounds (up to 64 Q
         // sources, at least every one at or below c') or commit the round.  Every
         // kernel reads the decision from device memory, so the host only checks
         // for the end every few iterations.
         const int per_sync = 32;
-        for (;;) {
+        const hipStream_t caller = s;
+        Replay rp;
+        auto record = [&](hipStream_t q) {
+            const hipStream_t keep = s;
+            s = q;
+            const MsPlanes P = PL.view(PL.qmax);
             for (int r = 0; r < per_sync; ++r) {
-                ++epoch;
                 launch_round_reset(st.p, s);
                 launch_reduce(deg.p, nullptr, alive.p, n, st.p, s);
                 launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, s);
@@ -775,21 +824,35 @@ struct ExactRun {
                 ms_batch(P, g->items, n, g->rp, g->col, alive.p, adeg.p, srcl.p, 0, &st.p->ms_ns, h, deg.p, st.p, s);
                 launch_mark_exact(srcl.p, st.p, exact.p, s);
                 launch_round_begin_gated(st.p, s);
-                launch_select_gated(deg.p, alive.p, n, st.p, core.p, rlist.p, mark.p, epoch, s);
-                delete_round_masked(epoch);
+                launch_select_gated(deg.p, alive.p, n, st.p, core.p, rlist.p, mark.p, -1, s);
+                delete_round_masked(-1);
                 launch_anchor(alist.p, &st.p->aff_fill, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 1, s);
                 launch_decay_masked(alist.p, st.p, hopfill.p, h, alive.p, adeg.p, anchor.p, rmask.p, deg.p, exact.p,
                                     s);
                 launch_clear_u64_list(alist.p, &st.p->aff_fill, rmask.p, s);
                 launch_clear_u64_list(rlist.p, &st.p->rcount, rmask.p, s);
             }
+            s = keep;
+        };
+        const bool use_graph = !graphs_off() && !ctx->prof_on;
+        PL.timer = ctx->prof_on ? &ctx->timer[0] : nullptr;
+        const hipStream_t q = rp.prepare(caller, use_graph, record);
+        for (;;) {
+            rp.run(record);
+            if (ctx->prof_on) prof_collect(ctx);
             iters += per_sync;
-            read_state(ctx, st.p, s);
+            read_state(ctx, st.p, q);
             const RoundState hs = *ctx->host_state;
             if (hs.mode == 2) break;
             if (iters > 4ll * n + 4096) fail(KH_EDEVICE);
+            if (hs.fepoch > (1 << 30)) {
+                // frontier marks are compared for equality only: restart their epochs
+                launch_fill_i32(fmark.p, 0, n, q);
+                launch_set_int(&st.p->fepoch, 0, q);
+            }
             trace_round(hs, "lazy", t0);
         }
+        hip_ok(hipStreamSynchronize(q));
         fin = *ctx->host_state;
         prof_add_counters(ctx, fin);
     }
@@ -978,38 +1041,43 @@ struct SampledRun {
         const int32_t n = g->n;
         const int64_t* key = key_ext ? key_ext : d.p;
         int32_t* changed[2] = {chA.p, chB.p};
-        int32_t epoch = 0;
         const int batch = 8;
         const auto t_start = Clock::now();
-        for (;;) {
+        PullTimer* utimer = ctx->prof_on ? &ctx->timer[1] : nullptr;
+        const hipStream_t caller = s;
+        Replay rp;
+        auto record = [&](hipStream_t q) {
             for (int r = 0; r < batch; ++r) {
-                launch_round_reset(st.p, s);
-                launch_reduce(key, d.p, alive.p, n, st.p, s);
-                launch_round_begin(st.p, ck.p, cs.p, cr.p, early_stop ? 1 : 0, s);
-                launch_select(key, alive.p, n, st.p, core.p, rlist.p, nullptr, 0, 1, s);
+                launch_round_reset(st.p, q);
+                launch_reduce(key, d.p, alive.p, n, st.p, q);
+                launch_round_begin(st.p, ck.p, cs.p, cr.p, early_stop ? 1 : 0, q);
+                launch_select(key, alive.p, n, st.p, core.p, rlist.p, nullptr, 0, 1, q);
                 for (int i = 1; i <= h; ++i) {
-                    ++epoch;
-                    launch_level_reset(st.p, i, s);
-                    launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
+                    launch_level_reset(st.p, i, q);
+                    launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, q);
                     if (i > 1)
                         launch_enqueue(changed[(i - 1) & 1], nullptr, &st.p->changed_count[(i - 1) & 1], g->rp, qv.p,
-                                       qb.p, &st.p->qcount, s);
-                    launch_expand_lists(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, rank.p, mark.p, epoch, i,
-                                        L.view(i - 1), L.view(i), lostmax.p, wl.p, &st.p->wl_count, s);
-                    launch_classify(wl.p, &st.p->wl_count, L.view(i), lostmax.p, rc.p, &st.p->rc_count, s);
+                                       qb.p, &st.p->qcount, q);
+                    launch_expand_lists(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, rank.p, mark.p, -1, i,
+                                        L.view(i - 1), L.view(i), lostmax.p, wl.p, &st.p->wl_count, st.p, q);
+                    launch_classify(wl.p, &st.p->wl_count, L.view(i), lostmax.p, rc.p, &st.p->rc_count, q);
                     if (i == 1)
                         launch_union1(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, L.view(1),
-                                      changed[1], &st.p->changed_count[1], st.p, s);
+                                      changed[1], &st.p->changed_count[1], st.p, q);
                     else
                         launch_union(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2,
                                      L.view(i - 1), L.view(i), cursor.p, order.p, changed[i & 1],
-                                     &st.p->changed_count[i & 1],
-                                     st.p, s);
+                                     &st.p->changed_count[i & 1], st.p, q, utimer);
                 }
                 launch_estimate(changed[h & 1], &st.p->changed_count[h & 1], n, alive.p, rank.p, L.size[h].p,
-                                L.kk[h].p, M, d.p, st.p, s);
+                                L.kk[h].p, M, d.p, st.p, q);
             }
-            read_state(ctx, st.p, s);
+        };
+        const hipStream_t q = rp.prepare(caller, !graphs_off() && !ctx->prof_on, record);
+        for (;;) {
+            rp.run(record);
+            if (ctx->prof_on) prof_collect(ctx);
+            read_state(ctx, st.p, q);
             if (ctx->host_state->alive_count == 0) break;
             // every round deletes at least the minimum vertex
             if (ctx->host_state->rounds > n + 1) fail(KH_EDEVICE);
@@ -1019,7 +1087,9 @@ struct SampledRun {
                              ctx->host_state->rcount, ctx->host_state->wl_count, ctx->host_state->rc_count,
                              std::chrono::duration<double>(Clock::now() - t_start).count());
         }
+        hip_ok(hipStreamSynchronize(q));
         fin = *ctx->host_state;
+        prof_add_counters(ctx, fin);
         cands = read_candidates(fin, ck, cs, cr, s);
     }
 };

@@ -52,16 +52,19 @@ struct RoundState {
     long long hi;            // recompute every inexact vertex whose bound is <= hi
     int hist[48];            // inexact vertices by bound - c: [0] <= 0, [b] in [2^(b-1), 2^b)
     int fcount[2];           // R-mask BFS frontier fills (ping-pong by hop parity)
+    int epoch;               // device-side mark epoch (advanced by the round / level resets)
+    int fepoch;              // device-side frontier-mark epoch (advanced per mask-BFS hop)
     int overflow;            // an estimate exceeded the representable range
     unsigned long long te;     // edges traversed (exact h-degree work)
     unsigned long long arcs;   // adjacency entries read by the h-degree kernels
     unsigned long long elems;  // sample-list entries read by the union kernels
     unsigned long long pull_bytes;   // algorithmic bytes of the pull kernel (without neighbour gathers)
     unsigned long long pull_gather;  // bytes of neighbour frontier words gathered by the pull kernel
+    unsigned long long union_bytes;  // algorithmic bytes of the level >= 2 union kernel
 };
 
-// Optional HIP-event timing of every launch of the h-degree pull kernel, on the
-// stream it is launched on.
+// Optional HIP-event timing of every launch of a kernel, on the stream it is
+// launched on (slot 0: h-degree pull, slot 1: sample-list union).
 struct PullTimer {
     hipEvent_t* ev = nullptr;  // pairs: ev[2i] before, ev[2i+1] after launch i
     int cap = 0;
@@ -136,7 +139,7 @@ void launch_rbfs_hop_reset(RoundState* st, int t, hipStream_t s);
 void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
                         const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
                         int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
-                        int32_t* alist, int* aff_fill, hipStream_t s);
+                        int32_t* alist, int* aff_fill, RoundState* st, hipStream_t s);
 void launch_clear_u64_list(const int32_t* list, const int* count, uint64_t* arr, hipStream_t s);
 // exact decrement for vertices at distance exactly h (deg -= |R within h|), bound otherwise
 void launch_decay_masked(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
@@ -204,14 +207,14 @@ void launch_union1(const int32_t* worklist, const int* wl_count, int32_t n, cons
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
                   const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, LevelView prev, LevelView cur,
                   int32_t* cursor, int32_t* order, int32_t* changed, int* changed_count, RoundState* st,
-                  hipStream_t s);
+                  hipStream_t s, PullTimer* timer = nullptr);
 // Propagate the deletions and changes of level i-1 over the arcs of the queued
 // vertices: mark + append alive neighbours, fold the highest lost rank into
 // lostmax[], and keep m[.,i] current.
 void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp,
                          const int32_t* col, const uint8_t* alive, const uint8_t* rank, int32_t* mark, int32_t epoch,
                          int level, LevelView prev, LevelView cur, int32_t* lostmax, int32_t* out, int* out_count,
-                         hipStream_t s);
+                         RoundState* st, hipStream_t s);
 // Keep only the worklist vertices whose list can change.
 void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int32_t* lostmax, int32_t* rc,
                      int* rc_count, hipStream_t s);

@@ -218,11 +218,12 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
     const int hcap = 1 << hash_log2;
     HashSet H{tab, (uint32_t)(hcap - 1), 32 - hash_log2, &s_count, hist, M};
     const int total = worklist ? *wl_count : n;
-    unsigned long long elems = 0;
+    unsigned long long elems = 0, bytes = 0;
     for (int wi = blockIdx.x; wi < total; wi += gridDim.x) {
         const int32_t v = worklist ? worklist[wi] : wi;
         if (!alive[v]) continue;
         const int32_t b = rp[v], e = rp[v + 1];
+        if (tid == 0) bytes += 8 + 14 + 22ull * (unsigned long long)(e - b);  // rp, vertex state, per-arc metadata
         // hubs: order the arcs by the head rank of the neighbour's list so that
         // level L only visits the neighbours whose list reaches rank L
         const bool hub = (e - b) > kHubDegree;
@@ -304,6 +305,7 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
                     if (*(volatile int*)&s_count <= M) hs_insert(H, key);
                 }
                 elems += (unsigned long long)(c - c0 + 1);
+                bytes += 25 + 4ull * (unsigned long long)(c - c0 + 1) + (c != c0 ? 4 : 0);
                 if (c != c0) cursor[p] = c;
             }
             if (tid == 0 && rank[v] == L && *(volatile int*)&s_count <= M) hs_insert(H, sample_key(L, v));
@@ -337,6 +339,7 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
                 const uint32_t key = out[t];
                 if (!hs_contains(H, key)) lm = max(lm, key_rank(key));
             }
+            if (tid == 0) bytes += 4ull * (unsigned long long)s_os;
             lm = wave_max_i(lm);
             if (lane_id() == 0 && lm >= 0) atomicMax(&s_lost, lm);
             __syncthreads();
@@ -349,6 +352,7 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             }
         }
         if (tid == 0) {
+            bytes += 4ull * (unsigned long long)s_size + 13;
             cur.size[v] = s_size;
             cur.k[v] = (uint8_t)s_k;
             cur.m[v] = hk[s_k];
@@ -362,13 +366,17 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
         __syncthreads();
     }
     elems = (unsigned long long)wave_sum_ll((long long)elems);
-    if (lane_id() == 0 && elems) atomicAdd(&st->elems, elems);
+    bytes = (unsigned long long)wave_sum_ll((long long)bytes);
+    if (lane_id() == 0) {
+        if (elems) atomicAdd(&st->elems, elems);
+        if (bytes) atomicAdd(&st->union_bytes, bytes);
+    }
 }
 
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
                   const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, LevelView prev, LevelView cur,
                   int32_t* cursor, int32_t* order, int32_t* changed, int* changed_count, RoundState* st,
-                  hipStream_t s) {
+                  hipStream_t s, PullTimer* timer) {
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
     const size_t lds = sizeof(uint32_t) << hash_log2;
@@ -377,8 +385,14 @@ void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const
         (void)hipFuncSetAttribute((const void*)k_union, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         lds_set = lds;
     }
+    const bool timed = timer && timer->used < timer->cap;
+    if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
     hipLaunchKernelGGL(k_union, dim3(grid), dim3(kUnionThreads), lds, s, worklist, wl_count, n, rp, col, alive, rank,
                        M, hash_log2, prev, cur, cursor, order, changed, changed_count, st);
+    if (timed) {
+        (void)hipEventRecord(timer->ev[2 * timer->used + 1], s);
+        timer->used += 1;
+    }
 }
 
 // ---- propagation of deletions and changes to the next level ---------------------------------
@@ -391,7 +405,9 @@ __global__ void k_expand_lists(const int32_t* __restrict__ qv, const int32_t* __
                                const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
                                int32_t* __restrict__ mark, int32_t epoch, int level, LevelView prev, LevelView cur,
-                               int32_t* __restrict__ lostmax, int32_t* __restrict__ out, int* out_count) {
+                               int32_t* __restrict__ lostmax, int32_t* __restrict__ out, int* out_count,
+                               RoundState* st) {
+    if (epoch < 0) epoch = st->epoch;
     const int nq = *qcount;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
@@ -434,9 +450,9 @@ __global__ void k_expand_lists(const int32_t* __restrict__ qv, const int32_t* __
 void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp,
                          const int32_t* col, const uint8_t* alive, const uint8_t* rank, int32_t* mark, int32_t epoch,
                          int level, LevelView prev, LevelView cur, int32_t* lostmax, int32_t* out, int* out_count,
-                         hipStream_t s) {
+                         RoundState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_expand_lists, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, rank, mark, epoch,
-                       level, prev, cur, lostmax, out, out_count);
+                       level, prev, cur, lostmax, out, out_count, st);
 }
 
 // A list can only change when (cut) a member of rank >= k-1 left some input

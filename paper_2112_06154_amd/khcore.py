@@ -106,7 +106,7 @@ def lib():
         L.kh_dense.restype = i32
         L.kh_profile_enable.argtypes = [P, i32]
         L.kh_profile_enable.restype = i32
-        L.kh_profile_read.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(i64),
+        L.kh_profile_read.argtypes = [P, i32, ctypes.POINTER(i64), ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                       ctypes.POINTER(i64)]
         L.kh_profile_read.restype = i32
         _lib = L
@@ -171,10 +171,11 @@ class Context:
         """Start (resetting totals) or stop HIP-event timing of the h-degree pull kernel."""
         _check(lib().kh_profile_enable(self.handle, int(on)), "kh_profile_enable")
 
-    def profile_read(self) -> dict:
+    def profile_read(self, kernel: int = 0) -> dict:
+        """Totals for kernel 0 (h-degree pull) or 1 (sample-list union)."""
         la, by, ga = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         ms = ctypes.c_double()
-        _check(lib().kh_profile_read(self.handle, ctypes.byref(la), ctypes.byref(ms), ctypes.byref(by),
+        _check(lib().kh_profile_read(self.handle, kernel, ctypes.byref(la), ctypes.byref(ms), ctypes.byref(by),
                                      ctypes.byref(ga)), "kh_profile_read")
         return {"launches": la.value, "ms": ms.value, "alg_bytes": by.value, "gather_bytes": ga.value}
 

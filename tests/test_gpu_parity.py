@@ -184,3 +184,26 @@ def test_dense_sampled_matches_oracle(ctx):
                 want = oracle.dense(g, got, h, "sampled", oracle.ranks(g.n, 21, 1), 40, prune=prune, eps=0.5)
                 assert res["M_dense_used"] == 40
                 assert (res["dense_k"], res["dense_size"], res["dense_R"]) == (want["k"], want["size"], want["R"])
+
+
+def test_graph_replay_matches_direct_launches(ctx, monkeypatch):
+    # The round loops replay captured kernel sequences; launching the same
+    # kernels directly must give the same numbers, run after run.
+    g = gg.barabasi_albert(1500, 3, seed=4)
+    G = kh.Graph.from_gg(ctx, g)
+    for h in (2, 3):
+        say("graph vs direct", h)
+        want_e = oracle.exact_core(g, h)
+        want_s = oracle.sampled_core(g, h, oracle.ranks(g.n, 5), 20)
+        for _ in range(2):
+            monkeypatch.delenv("KH_NO_GRAPH", raising=False)
+            ge, _ = kh.core(G, h)
+            gs, _ = kh.core(G, h, epsilon=0.5, seed=5, M_override=20)
+            monkeypatch.setenv("KH_NO_GRAPH", "1")
+            de, _ = kh.core(G, h)
+            ds, _ = kh.core(G, h, epsilon=0.5, seed=5, M_override=20)
+            for got in (ge, de):
+                assert np.array_equal(got.astype(np.int64), want_e)
+            for got in (gs, ds):
+                assert np.array_equal(got.astype(np.int64), want_s)
+        monkeypatch.delenv("KH_NO_GRAPH", raising=False)
