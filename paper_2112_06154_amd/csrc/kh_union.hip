@@ -197,10 +197,103 @@ __device__ __forceinline__ bool hs_contains(const HashSet& H, uint32_t key) {
     }
 }
 
+// Block-wide exclusive scan of one int per thread (blockDim.x == kUnionThreads).
+__device__ __forceinline__ int block_excl_scan_i(int v, int* sh, int* total) {
+    const int l = lane_id();
+    const int w = threadIdx.x >> 6;
+    const int x = wave_incl_scan(v);
+    if (l == 63) sh[w] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kUnionThreads / 64; ++i) {
+        if (i < w) off += sh[i];
+        tot += sh[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+// One flattened pass: insert every list entry with rank in [lo, ...) that sits
+// at or after the arc's cursor, i.e. the next run of entries of rank >= lo
+// (lists are grouped by rank, highest first, and every entry before the cursor
+// has a higher rank than any pass still to come).  Arcs go 256 at a time: each
+// thread finds its arc's run, a block scan lays the runs end to end, and all
+// threads then insert entries of any run.
+__device__ void union_pass(int lo, int32_t b, int32_t span, bool hub, const int32_t* __restrict__ order,
+                           const int32_t* __restrict__ col, const uint8_t* __restrict__ alive, const LevelView& prev,
+                           int32_t* __restrict__ cursor, const HashSet& H, int M, int* s_lens, int* s_offs,
+                           long long* s_seg, int* s_scan, unsigned long long& elems, unsigned long long& bytes) {
+    const int tid = threadIdx.x;
+    for (int32_t c0 = 0; c0 < span; c0 += kUnionThreads) {
+        const int32_t i = c0 + tid;
+        int len = 0;
+        long long seg = 0;
+        if (i < span) {
+            const int32_t p = hub ? order[b + i] : b + i;
+            const int32_t w = col[p];
+            bytes += hub ? 9 : 5;
+            if (alive[w]) {
+                const int sz = prev.size[w];
+                int cur = cursor[p];
+                bytes += 8;
+                if (cur < sz) {
+                    const uint32_t* lst = prev.keys + prev.off[w];
+                    bytes += 12;
+                    if (key_rank(lst[cur]) >= lo) {
+                        int end;
+                        if (key_rank(lst[sz - 1]) >= lo) {
+                            end = sz;
+                        } else {
+                            // first entry of rank < lo (ranks never increase along a list)
+                            int a = cur + 1, z = sz - 1;
+                            while (a < z) {
+                                const int mid = (a + z) >> 1;
+                                if (key_rank(lst[mid]) >= lo) a = mid + 1; else z = mid;
+                            }
+                            end = a;
+                            bytes += 4 * 10;
+                        }
+                        len = end - cur;
+                        seg = prev.off[w] + cur;
+                        cursor[p] = end;
+                        bytes += 4;
+                    }
+                }
+            }
+        }
+        s_lens[tid] = len;
+        s_seg[tid] = seg;
+        int tot;
+        const int off = block_excl_scan_i(len, s_scan, &tot);
+        s_offs[tid] = off;
+        __syncthreads();
+        for (int j = tid; j < tot; j += kUnionThreads) {
+            // the run holding entry j: last a with offs[a] <= j
+            int a = 0, z = kUnionThreads - 1;
+            while (a < z) {
+                const int mid = (a + z + 1) >> 1;
+                if (s_offs[mid] <= j) a = mid; else z = mid - 1;
+            }
+            const uint32_t key = prev.keys[s_seg[a] + (j - s_offs[a])];
+            if (*(volatile int*)H.count <= M) hs_insert(H, key);
+        }
+        elems += (unsigned long long)(tid == 0 ? tot : 0);
+        bytes += tid == 0 ? 4ull * (unsigned long long)tot : 0ull;
+        __syncthreads();
+    }
+}
+
 // Besides B[v,i] and k[v,i] this writes m[v,i] (alive neighbours whose
 // k[w,i-1] equals the new k[v,i]), the cut flag (k[v,i] above every
 // neighbour's level, i.e. fixed by the M threshold), and for a changed list the
 // highest rank among its members that are not in the new list.
+//
+// On a recomputation (changed != NULL) the old k[v,i] bounds the new one from
+// above and the old list held every member of rank >= old k, at most M of
+// them; removing vertices only shrinks N(v;i).  So all entries of rank >= old k
+// are inserted in one pass, and the level-by-level search only runs below it.
 __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ worklist, const int* wl_count, int32_t n,
                                                const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
@@ -210,8 +303,10 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
     extern __shared__ uint32_t tab[];
     __shared__ int hist[256];
     __shared__ int hk[256];
-    __shared__ int hh[256];   // hubs: neighbours by head rank, then scatter cursors
+    __shared__ int hh[256];    // hubs: neighbours by head rank, then scatter cursors
     __shared__ int hcum[257];  // hubs: neighbours whose list head rank is >= L
+    __shared__ int s_lens[kUnionThreads], s_offs[kUnionThreads], s_scan[kUnionThreads / 64];
+    __shared__ long long s_seg[kUnionThreads];
     __shared__ int s_kmax, s_htop, s_count, s_k, s_size, s_ok, s_os, s_lost;
     const int tid = threadIdx.x;
     const int bs = blockDim.x;
@@ -224,8 +319,8 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
         if (!alive[v]) continue;
         const int32_t b = rp[v], e = rp[v + 1];
         if (tid == 0) bytes += 8 + 14 + 22ull * (unsigned long long)(e - b);  // rp, vertex state, per-arc metadata
-        // hubs: order the arcs by the head rank of the neighbour's list so that
-        // level L only visits the neighbours whose list reaches rank L
+        // hubs: order the arcs by the head rank of the neighbour's list so that a
+        // pass at rank >= L only visits the neighbours whose list reaches rank L
         const bool hub = (e - b) > kHubDegree;
         for (int t = tid; t < hcap; t += bs) tab[t] = kEmptyKey;
         hist[tid] = 0;
@@ -284,32 +379,21 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             __syncthreads();
         }
         const int kmax = s_kmax;
+        const int htop = s_htop;
+        const int rv = rank[v];
         int k = kmax;
-        for (int L = s_htop; L >= kmax; --L) {
-            const int32_t span = hub ? hcum[L] : e - b;
-            for (int32_t i = tid; i < span; i += bs) {
-                const int32_t p = hub ? order[b + i] : b + i;
-                const int32_t w = col[p];
-                if (!alive[w]) continue;
-                int c = cursor[p];
-                const int sz = prev.size[w];
-                if (c >= sz) continue;
-                const uint32_t* lst = prev.keys + prev.off[w];
-                const int c0 = c;
-                while (c < sz) {
-                    const uint32_t key = lst[c];
-                    if (key_rank(key) != L) break;
-                    ++c;
-                    // once more than M distinct keys are in, rank L is cut anyway; each
-                    // thread inserts at most one key after that, so the table stays half empty
-                    if (*(volatile int*)&s_count <= M) hs_insert(H, key);
-                }
-                elems += (unsigned long long)(c - c0 + 1);
-                bytes += 25 + 4ull * (unsigned long long)(c - c0 + 1) + (c != c0 ? 4 : 0);
-                if (c != c0) cursor[p] = c;
-            }
-            if (tid == 0 && rank[v] == L && *(volatile int*)&s_count <= M) hs_insert(H, sample_key(L, v));
-            __syncthreads();
+        // first pass: every rank >= lo0 at once (the old level on a recomputation)
+        const int lo0 = (changed && s_ok >= kmax && s_ok <= htop) ? s_ok : htop + 1;
+        if (lo0 <= htop) {
+            if (tid == 0 && rv >= lo0) hs_insert(H, sample_key(rv, v));
+            union_pass(lo0, b, hub ? hcum[lo0] : e - b, hub, order, col, alive, prev, cursor, H, M, s_lens, s_offs,
+                       s_seg, s_scan, elems, bytes);
+        }
+        // then one rank at a time down to kmax, stopping once more than M are in
+        for (int L = min(lo0 - 1, htop); L >= kmax; --L) {
+            if (tid == 0 && rv == L && *(volatile int*)&s_count <= M) hs_insert(H, sample_key(L, v));
+            union_pass(L, b, hub ? hcum[L] : e - b, hub, order, col, alive, prev, cursor, H, M, s_lens, s_offs,
+                       s_seg, s_scan, elems, bytes);
             const int over = s_count > M;
             __syncthreads();
             if (over) {
