@@ -903,6 +903,7 @@ struct Lists {
     std::vector<Buf<uint32_t>> keys;
     std::vector<Buf<int32_t>> size, m;
     std::vector<Buf<uint8_t>> kk, cut, kold;
+    std::vector<Buf<uint32_t>> meta;
     std::vector<Buf<int16_t>> lost;
     std::vector<int64_t> total;
     LevelView view(int i) const {
@@ -916,6 +917,7 @@ struct Lists {
         L.cut = cut[i].p;
         L.lost = lost[i].p;
         L.kold = kold[i].p;
+        L.meta = meta[i].p;
         return L;
     }
 };
@@ -986,6 +988,7 @@ struct SampledRun {
         L.cut.resize(h + 1);
         L.kold.resize(h + 1);
         L.lost.resize(h + 1);
+        L.meta.resize(h + 1);
         L.total.assign(h + 1, 0);
         for (int i = 1; i <= h; ++i) {
             L.cap[i].alloc(ctx, n);
@@ -1006,6 +1009,7 @@ struct SampledRun {
             L.cut[i].alloc(ctx, n);
             L.kold[i].alloc(ctx, n);
             L.lost[i].alloc(ctx, n);
+            L.meta[i].alloc(ctx, n);
         }
         for (int i = 1; i < h; ++i) L.cap[i].release();
         if (h >= 1) L.cap[h].release();

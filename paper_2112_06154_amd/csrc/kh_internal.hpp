@@ -194,6 +194,7 @@ struct LevelView {
     uint8_t* cut;        // 1 if k[v,i] was set by the M threshold (k > max_w k[w,i-1])
     int16_t* lost;       // for vertices changed this round: highest rank that left B[v,i] (-1: none)
     uint8_t* kold;       // for vertices changed this round: k[v,i] before the change
+    uint32_t* meta;      // packed |B[v,i]| (bits 0-15) | k[v,i] (16-23) | rank of the first entry (24-31)
 };
 
 void launch_cap_level1(const int32_t* rp, int32_t n, int32_t M, int64_t* cap, hipStream_t s);

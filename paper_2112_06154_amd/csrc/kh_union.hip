@@ -23,6 +23,14 @@ namespace kh {
 
 __device__ __forceinline__ uint32_t* keys_at(const LevelView& L, int32_t v) { return L.keys + L.off[v]; }
 
+// Packed per-list header: one 4-byte read instead of three scattered ones.
+__device__ __forceinline__ uint32_t pack_meta(int size, int k, int head_rank) {
+    return (uint32_t)size | ((uint32_t)k << 16) | ((uint32_t)(head_rank & 255) << 24);
+}
+__device__ __forceinline__ int meta_size(uint32_t m) { return (int)(m & 0xFFFFu); }
+__device__ __forceinline__ int meta_k(uint32_t m) { return (int)((m >> 16) & 0xFFu); }
+__device__ __forceinline__ int meta_head(uint32_t m) { return (int)(m >> 24); }
+
 __global__ void k_cap_level1(const int32_t* __restrict__ rp, int32_t n, int32_t M, int64_t* __restrict__ cap) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         const int64_t c = 1 + (int64_t)(rp[v + 1] - rp[v]);
@@ -69,7 +77,7 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
                                                 int32_t M, LevelView cur, int32_t* __restrict__ changed,
                                                 int* changed_count, RoundState* st) {
     __shared__ int hist[256];
-    __shared__ int s_k, s_size, s_nb, s_ok, s_os, s_lost;
+    __shared__ int s_k, s_size, s_nb, s_ok, s_os, s_lost, s_head;
     const int tid = threadIdx.x;
     const int total = worklist ? *wl_count : n;
     unsigned long long elems = 0;
@@ -103,14 +111,17 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
                 run += hist[L];
             }
             run = 0;
+            int hr = 0;
             for (int L = 255; L >= k; --L) {
                 const int c = hist[L];
-                hist[L] = run;  // becomes the write cursor of rank group L
+                if (c > 0 && run == 0) hr = L;  // highest nonempty rank group
+                hist[L] = run;                  // becomes the write cursor of rank group L
                 run += c;
             }
             s_k = k;
             s_size = run;
             s_nb = all - 1;
+            s_head = hr;
         }
         __syncthreads();
         const int k = s_k;
@@ -138,6 +149,7 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
             if (rv >= k) out[atomicAdd(&hist[rv], 1)] = sample_key(rv, v);
             cur.size[v] = s_size;
             cur.k[v] = (uint8_t)k;
+            cur.meta[v] = pack_meta(s_size, k, s_head);
             cur.m[v] = k == 0 ? s_nb : 0;
             cur.cut[v] = k > 0 ? 1 : 0;
             if (chg) {
@@ -215,16 +227,75 @@ __device__ __forceinline__ int block_excl_scan_i(int v, int* sh, int* total) {
     return off + x - v;
 }
 
-// One flattened pass: insert every list entry with rank in [lo, ...) that sits
-// at or after the arc's cursor, i.e. the next run of entries of rank >= lo
-// (lists are grouped by rank, highest first, and every entry before the cursor
-// has a higher rank than any pass still to come).  Arcs go 256 at a time: each
-// thread finds its arc's run, a block scan lays the runs end to end, and all
-// threads then insert entries of any run.
-__device__ void union_pass(int lo, int32_t b, int32_t span, bool hub, const int32_t* __restrict__ order,
-                           const int32_t* __restrict__ col, const uint8_t* __restrict__ alive, const LevelView& prev,
-                           int32_t* __restrict__ cursor, const HashSet& H, int M, int* s_lens, int* s_offs,
-                           long long* s_seg, int* s_scan, unsigned long long& elems, unsigned long long& bytes) {
+// One flattened pass: insert every list entry of rank >= lo that sits at or
+// after the arc's cursor, i.e. the next run of entries of rank >= lo (lists are
+// grouped by rank, highest first, and every entry before the cursor has a
+// higher rank than any pass still to come).  Each thread owns one arc per
+// chunk; a block scan lays the runs end to end and all threads then insert
+// entries of any run.
+struct ArcState {  // one arc of the current vertex, kept in registers across passes
+    int64_t off;
+    int size;
+    int cur;
+};
+
+__device__ __forceinline__ int arc_run(const uint32_t* __restrict__ lst, ArcState& a, int lo,
+                                       unsigned long long& bytes) {
+    if (a.cur >= a.size) return 0;
+    bytes += 4;
+    if (key_rank(lst[a.cur]) < lo) return 0;
+    int end;
+    bytes += 4;
+    if (key_rank(lst[a.size - 1]) >= lo) {
+        end = a.size;
+    } else {
+        // first entry of rank < lo (ranks never increase along a list)
+        int x = a.cur + 1, z = a.size - 1;
+        while (x < z) {
+            const int mid = (x + z) >> 1;
+            if (key_rank(lst[mid]) >= lo) x = mid + 1; else z = mid;
+            bytes += 4;
+        }
+        end = x;
+    }
+    const int len = end - a.cur;
+    a.cur = end;
+    return len;
+}
+
+__device__ __forceinline__ void insert_runs(int len, long long seg, const LevelView& prev, const HashSet& H, int M,
+                                            int* s_offs, long long* s_seg, int* s_scan,
+                                            unsigned long long& elems, unsigned long long& bytes) {
+    const int tid = threadIdx.x;
+    s_seg[tid] = seg;
+    int tot;
+    const int off = block_excl_scan_i(len, s_scan, &tot);
+    s_offs[tid] = off;
+    __syncthreads();
+    for (int j = tid; j < tot; j += kUnionThreads) {
+        // the run holding entry j: last a with offs[a] <= j
+        int a = 0, z = kUnionThreads - 1;
+        while (a < z) {
+            const int mid = (a + z + 1) >> 1;
+            if (s_offs[mid] <= j) a = mid; else z = mid - 1;
+        }
+        const uint32_t key = prev.keys[s_seg[a] + (j - s_offs[a])];
+        if (*(volatile int*)H.count <= M) hs_insert(H, key);
+    }
+    if (tid == 0) {
+        elems += (unsigned long long)tot;
+        bytes += 4ull * (unsigned long long)tot;
+    }
+    __syncthreads();
+}
+
+// Vertices with more than kUnionThreads neighbours: arcs in chunks, cursors in
+// global scratch (hubs visit only the arcs whose list head reaches lo).
+__device__ void union_pass_wide(int lo, int32_t b, int32_t span, bool hub, const int32_t* __restrict__ order,
+                                const int32_t* __restrict__ col, const uint8_t* __restrict__ alive,
+                                const LevelView& prev, int32_t* __restrict__ cursor, const HashSet& H, int M,
+                                int* s_offs, long long* s_seg, int* s_scan, unsigned long long& elems,
+                                unsigned long long& bytes) {
     const int tid = threadIdx.x;
     for (int32_t c0 = 0; c0 < span; c0 += kUnionThreads) {
         const int32_t i = c0 + tid;
@@ -235,53 +306,24 @@ __device__ void union_pass(int lo, int32_t b, int32_t span, bool hub, const int3
             const int32_t w = col[p];
             bytes += hub ? 9 : 5;
             if (alive[w]) {
-                const int sz = prev.size[w];
-                int cur = cursor[p];
+                ArcState a;
+                a.size = meta_size(prev.meta[w]);
+                a.cur = cursor[p];
                 bytes += 8;
-                if (cur < sz) {
-                    const uint32_t* lst = prev.keys + prev.off[w];
-                    bytes += 12;
-                    if (key_rank(lst[cur]) >= lo) {
-                        int end;
-                        if (key_rank(lst[sz - 1]) >= lo) {
-                            end = sz;
-                        } else {
-                            // first entry of rank < lo (ranks never increase along a list)
-                            int a = cur + 1, z = sz - 1;
-                            while (a < z) {
-                                const int mid = (a + z) >> 1;
-                                if (key_rank(lst[mid]) >= lo) a = mid + 1; else z = mid;
-                            }
-                            end = a;
-                            bytes += 4 * 10;
-                        }
-                        len = end - cur;
-                        seg = prev.off[w] + cur;
-                        cursor[p] = end;
+                if (a.cur < a.size) {
+                    a.off = prev.off[w];
+                    bytes += 8;
+                    const int start = a.cur;
+                    len = arc_run(prev.keys + a.off, a, lo, bytes);
+                    if (len) {
+                        seg = a.off + start;
+                        cursor[p] = a.cur;
                         bytes += 4;
                     }
                 }
             }
         }
-        s_lens[tid] = len;
-        s_seg[tid] = seg;
-        int tot;
-        const int off = block_excl_scan_i(len, s_scan, &tot);
-        s_offs[tid] = off;
-        __syncthreads();
-        for (int j = tid; j < tot; j += kUnionThreads) {
-            // the run holding entry j: last a with offs[a] <= j
-            int a = 0, z = kUnionThreads - 1;
-            while (a < z) {
-                const int mid = (a + z + 1) >> 1;
-                if (s_offs[mid] <= j) a = mid; else z = mid - 1;
-            }
-            const uint32_t key = prev.keys[s_seg[a] + (j - s_offs[a])];
-            if (*(volatile int*)H.count <= M) hs_insert(H, key);
-        }
-        elems += (unsigned long long)(tid == 0 ? tot : 0);
-        bytes += tid == 0 ? 4ull * (unsigned long long)tot : 0ull;
-        __syncthreads();
+        insert_runs(len, seg, prev, H, M, s_offs, s_seg, s_scan, elems, bytes);
     }
 }
 
@@ -305,9 +347,9 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
     __shared__ int hk[256];
     __shared__ int hh[256];    // hubs: neighbours by head rank, then scatter cursors
     __shared__ int hcum[257];  // hubs: neighbours whose list head rank is >= L
-    __shared__ int s_lens[kUnionThreads], s_offs[kUnionThreads], s_scan[kUnionThreads / 64];
+    __shared__ int s_offs[kUnionThreads], s_scan[kUnionThreads / 64];
     __shared__ long long s_seg[kUnionThreads];
-    __shared__ int s_kmax, s_htop, s_count, s_k, s_size, s_ok, s_os, s_lost;
+    __shared__ int s_kmax, s_htop, s_count, s_k, s_size, s_ok, s_os, s_lost, s_head;
     const int tid = threadIdx.x;
     const int bs = blockDim.x;
     const int hcap = 1 << hash_log2;
@@ -318,10 +360,13 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
         const int32_t v = worklist ? worklist[wi] : wi;
         if (!alive[v]) continue;
         const int32_t b = rp[v], e = rp[v + 1];
-        if (tid == 0) bytes += 8 + 14 + 22ull * (unsigned long long)(e - b);  // rp, vertex state, per-arc metadata
+        const int32_t deg = e - b;
+        if (tid == 0) bytes += 8 + 6;  // rp[v], rank/alive/old state of v
+        // small vertices: thread tid owns arc b + tid for the whole computation;
         // hubs: order the arcs by the head rank of the neighbour's list so that a
         // pass at rank >= L only visits the neighbours whose list reaches rank L
-        const bool hub = (e - b) > kHubDegree;
+        const bool small = deg <= kUnionThreads;
+        const bool hub = deg > kHubDegree;
         for (int t = tid; t < hcap; t += bs) tab[t] = kEmptyKey;
         hist[tid] = 0;
         hk[tid] = 0;
@@ -336,17 +381,27 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
         }
         __syncthreads();
         int kmax_l = 0, htop_l = -1;
+        ArcState mine{0, 0, 0};
         for (int32_t p = b + tid; p < e; p += bs) {
             const int32_t w = col[p];
-            cursor[p] = 0;
+            bytes += 5;
+            if (!small) cursor[p] = 0;
             if (alive[w]) {
-                const int kw = prev.k[w];
+                const uint32_t mt = prev.meta[w];
+                bytes += 4;
+                const int kw = meta_k(mt);
+                const int sz = meta_size(mt);
                 atomicAdd(&hk[kw], 1);
                 kmax_l = kw > kmax_l ? kw : kmax_l;
-                if (prev.size[w] > 0) {
-                    const int hr = key_rank(prev.keys[prev.off[w]]);
+                if (sz > 0) {
+                    const int hr = meta_head(mt);
                     htop_l = hr > htop_l ? hr : htop_l;
                     if (hub) atomicAdd(&hh[hr], 1);
+                    if (small) {
+                        mine.size = sz;
+                        mine.off = prev.off[w];
+                        bytes += 8;
+                    }
                 }
             }
         }
@@ -371,11 +426,12 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             __syncthreads();
             for (int32_t p = b + tid; p < e; p += bs) {
                 const int32_t w = col[p];
-                if (alive[w] && prev.size[w] > 0) {
-                    const int hr = key_rank(prev.keys[prev.off[w]]);
-                    order[b + atomicAdd(&hh[hr], 1)] = p;
+                if (alive[w]) {
+                    const uint32_t mt = prev.meta[w];
+                    if (meta_size(mt) > 0) order[b + atomicAdd(&hh[meta_head(mt)], 1)] = p;
                 }
             }
+            bytes += tid == 0 ? 9ull * (unsigned long long)deg : 0ull;
             __syncthreads();
         }
         const int kmax = s_kmax;
@@ -386,14 +442,26 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
         const int lo0 = (changed && s_ok >= kmax && s_ok <= htop) ? s_ok : htop + 1;
         if (lo0 <= htop) {
             if (tid == 0 && rv >= lo0) hs_insert(H, sample_key(rv, v));
-            union_pass(lo0, b, hub ? hcum[lo0] : e - b, hub, order, col, alive, prev, cursor, H, M, s_lens, s_offs,
-                       s_seg, s_scan, elems, bytes);
+            if (small) {
+                const int start = mine.cur;
+                const int len = arc_run(prev.keys + mine.off, mine, lo0, bytes);
+                insert_runs(len, mine.off + start, prev, H, M, s_offs, s_seg, s_scan, elems, bytes);
+            } else {
+                union_pass_wide(lo0, b, hub ? hcum[lo0] : deg, hub, order, col, alive, prev, cursor, H, M, s_offs,
+                                s_seg, s_scan, elems, bytes);
+            }
         }
         // then one rank at a time down to kmax, stopping once more than M are in
         for (int L = min(lo0 - 1, htop); L >= kmax; --L) {
             if (tid == 0 && rv == L && *(volatile int*)&s_count <= M) hs_insert(H, sample_key(L, v));
-            union_pass(L, b, hub ? hcum[L] : e - b, hub, order, col, alive, prev, cursor, H, M, s_lens, s_offs,
-                       s_seg, s_scan, elems, bytes);
+            if (small) {
+                const int start = mine.cur;
+                const int len = arc_run(prev.keys + mine.off, mine, L, bytes);
+                insert_runs(len, mine.off + start, prev, H, M, s_offs, s_seg, s_scan, elems, bytes);
+            } else {
+                union_pass_wide(L, b, hub ? hcum[L] : deg, hub, order, col, alive, prev, cursor, H, M, s_offs,
+                                s_seg, s_scan, elems, bytes);
+            }
             const int over = s_count > M;
             __syncthreads();
             if (over) {
@@ -402,14 +470,16 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             }
         }
         if (tid == 0) {
-            int run = 0;
+            int run = 0, hr = 0;
             for (int L = 255; L >= k; --L) {
                 const int c = hist[L];
+                if (c > 0 && run == 0) hr = L;
                 hist[L] = run;
                 run += c;
             }
             s_k = k;
             s_size = run;
+            s_head = hr;
         }
         __syncthreads();
         const bool chg = changed && (s_ok != s_k || s_os != s_size);
@@ -436,9 +506,10 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             }
         }
         if (tid == 0) {
-            bytes += 4ull * (unsigned long long)s_size + 13;
+            bytes += 4ull * (unsigned long long)s_size + 17;
             cur.size[v] = s_size;
             cur.k[v] = (uint8_t)s_k;
+            cur.meta[v] = pack_meta(s_size, s_k, s_head);
             cur.m[v] = hk[s_k];
             cur.cut[v] = s_k > kmax ? 1 : 0;
             if (chg) {
@@ -506,8 +577,9 @@ __global__ void k_expand_lists(const int32_t* __restrict__ qv, const int32_t* __
             lw = rank[w];  // B[w,0] = {w}; only deleted vertices reach level 1
             kw_old = kw_new = 0;
         } else if (removed) {
-            lw = prev.size[w] > 0 ? key_rank(prev.keys[prev.off[w]]) : -1;
-            kw_old = kw_new = prev.k[w];
+            const uint32_t mt = prev.meta[w];
+            lw = meta_size(mt) > 0 ? meta_head(mt) : -1;
+            kw_old = kw_new = meta_k(mt);
         } else {
             lw = prev.lost[w];
             kw_old = prev.kold[w];
