@@ -200,12 +200,51 @@ def chung_lu(n: int, m: int, gamma: float, seed: int = 1, permute: bool = True) 
     return from_edges(n, e, f"cl_n{n}_m{m}_g{gamma}_s{seed}")
 
 
+_BA_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libggba.so")
+_ba_lib = None
+
+
+def build_native() -> str:
+    """Compile the C preferential-attachment drawer (ba.c) in place."""
+    import subprocess
+    src = os.path.join(os.path.dirname(_BA_LIB), "ba.c")
+    subprocess.run(["gcc", "-O2", "-shared", "-fPIC", "-o", _BA_LIB, src], check=True)
+    return _BA_LIB
+
+
+def _ba_native(n: int, k: int, key: int):
+    """Edge pairs from ba.c (same stream and order as the Python loop below),
+    or None when the library is not built."""
+    global _ba_lib
+    if _ba_lib is None:
+        if not os.path.exists(_BA_LIB):
+            return None
+        import ctypes
+        L = ctypes.CDLL(_BA_LIB)
+        L.gg_ba_edges.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p]
+        L.gg_ba_edges.restype = ctypes.c_int64
+        _ba_lib = L
+    if k > 64:
+        return None
+    pairs = k * (k + 1) // 2 + k * (n - k - 1)
+    out = np.empty(2 * pairs, dtype=np.int64)
+    got = _ba_lib.gg_ba_edges(n, k, key & 0xFFFFFFFFFFFFFFFF, out.ctypes.data)
+    if got != pairs:
+        raise RuntimeError("gg_ba_edges failed")
+    return out.reshape(-1, 2)
+
+
 def barabasi_albert(n: int, k: int = 3, seed: int = 1, permute: bool = True) -> Graph:
     """Preferential attachment: start from the clique K_{k+1}; every new vertex
     links to k distinct existing vertices chosen proportionally to degree."""
     if n <= k + 1:
         return clique(n)
     key = _key(seed, 0x4241)
+    e = _ba_native(n, k, key)
+    if e is not None:
+        if permute:
+            e = random_permutation(n, seed)[e]
+        return from_edges(n, e, f"ba_n{n}_k{k}_s{seed}")
     rnd = splitmix_stream(key, 0, 4 * k * n + 64)
     pos = 0
     ends = np.empty(2 * (k * (k + 1) // 2 + k * (n - k - 1)), dtype=np.int64)
@@ -295,6 +334,22 @@ def loguniform_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
 
 
 # ---- the named workloads -----------------------------------------------------
+
+def batch_workload(count: int = 4096, lo: int = 100, hi: int = 50_000, base_seed: int = 1) -> list:
+    """Many graphs of uneven size: n log-uniform on [lo, hi]; the first half
+    Erdos-Renyi with m = 3n (average degree 6), the second half
+    Barabasi-Albert with 3 edges per new vertex; graph i uses seed
+    base_seed + i."""
+    sizes = loguniform_sizes(count, lo, hi, base_seed)
+    out = []
+    for i in range(count):
+        n = int(sizes[i])
+        if i < count // 2:
+            out.append(erdos_renyi(n, 3 * n, base_seed + i))
+        else:
+            out.append(barabasi_albert(n, 3, base_seed + i))
+    return out
+
 
 def workload(name: str, seed: int = 1) -> Graph:
     """The single-graph synthetic workloads by name."""

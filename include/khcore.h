@@ -132,6 +132,27 @@ int64_t kh_graph_nnz(const kh_graph *g);
  * KH_EOVERFLOW (core number above INT32_MAX), KH_ENOMEM, KH_EDEVICE. */
 kh_status kh_core(kh_graph *g, const kh_params *params, int32_t *core_out, kh_result *res, void *stream);
 
+/* kh_core over `count` graphs at once (same params for all), for many small
+ * graphs that would each leave the GPU idle.  The graphs (all of this context)
+ * are packed on the device into disjoint unions and decomposed by one set of
+ * launches per union.  Components of a disjoint union do not interact
+ * (N(v;h,X) stays in v's graph, Sec. 2), so the core numbers are each graph's
+ * own; on the sampled path every vertex draws its rank from its id in its own
+ * graph and uses M of Eq. (buffer) with its own graph's n, so core_outs[i] is
+ * bit-identical to kh_core(graphs[i], params).
+ *   core_outs[count]: one int32 array of n_i entries per graph (host, or
+ *     device with KH_OUT_DEVICE); may be NULL for graphs with n = 0.
+ *   results (nullable) [count]: per graph M_used, max_core and, with
+ *     KH_WANT_DENSE, the dense_* fields of that graph; rounds, edges_traversed,
+ *     arcs_scanned, list_elements and seconds describe the packed union the
+ *     graph was part of (equal across its graphs).
+ * Unions hold at most 2^24 - 1 vertices (sampled) or 2^31 - 2 vertices and
+ * 2^31 - 1 arcs (exact); larger batches run as consecutive unions.
+ * Errors: as kh_core; KH_ENOTIMPL with KH_EARLY_STOP (its stopping test is per
+ * graph).  On error no result of the batch is valid. */
+kh_status kh_core_batch(kh_context *ctx, int32_t count, kh_graph *const *graphs, const kh_params *params,
+                        int32_t *const *core_outs, kh_result *results, void *stream);
+
 /* h-degrees deg_h(v;X) = |N(v;h,X)| - 1 (Sec. 2) of every vertex of X, where
  * X is given by alive[n] (uint8, nonzero = in X; device; NULL = all of V).
  * deg_out[n] (int32; host unless KH_OUT_DEVICE) gets -1 for v outside X.

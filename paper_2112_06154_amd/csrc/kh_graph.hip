@@ -23,10 +23,12 @@ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
     return z ^ (z >> 31);
 }
 
-__global__ void k_ranks(uint8_t* __restrict__ r, int32_t n, uint64_t seed, uint32_t sid) {
+__global__ void k_ranks(uint8_t* __restrict__ r, int32_t n, uint64_t seed, uint32_t sid,
+                        const int32_t* __restrict__ lid) {
     const uint64_t s0 = sm64(seed);
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        const uint64_t base = sm64(s0 ^ (uint64_t)(int64_t)v);
+        const int64_t id = lid ? lid[v] : v;
+        const uint64_t base = sm64(s0 ^ (uint64_t)id);
         int rank = 0;
         int j = 0;
         for (; j < 4; ++j) {
@@ -41,9 +43,49 @@ __global__ void k_ranks(uint8_t* __restrict__ r, int32_t n, uint64_t seed, uint3
     }
 }
 
-void launch_ranks(uint8_t* r, int32_t n, uint64_t seed, uint32_t sid, hipStream_t s) {
+void launch_ranks(uint8_t* r, int32_t n, uint64_t seed, uint32_t sid, hipStream_t s, const int32_t* lid) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_ranks, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, r, n, seed, sid);
+    hipLaunchKernelGGL(k_ranks, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, r, n, seed, sid, lid);
+}
+
+// ---- packing many graphs into one disjoint union ------------------------------------------
+__global__ void k_pack_col(int32_t count, const int64_t* __restrict__ a_off, const int32_t* __restrict__ v_off,
+                           const uint64_t* __restrict__ col_ptrs, int64_t nnz, int32_t* __restrict__ col) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x) {
+        // graph of arc i: last g with a_off[g] <= i
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a_off[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        const int32_t* src = reinterpret_cast<const int32_t*>(col_ptrs[lo]);
+        col[i] = src[i - a_off[lo]] + v_off[lo];
+    }
+}
+void launch_pack_col(int32_t count, const int64_t* a_off, const int32_t* v_off, const uint64_t* col_ptrs,
+                     int64_t nnz, int32_t* col, hipStream_t s) {
+    if (nnz > 0 && count > 0)
+        hipLaunchKernelGGL(k_pack_col, dim3(grid_for(nnz, 256, 16384)), dim3(256), 0, s, count, a_off, v_off,
+                           col_ptrs, nnz, col);
+}
+
+// dst_ptrs[g][i - v_off[g]] = src[i] for the vertices i of graph g
+__global__ void k_unpack_i32(int32_t count, const int32_t* __restrict__ v_off, const uint64_t* __restrict__ dst_ptrs,
+                             int32_t total, const int32_t* __restrict__ src) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (v_off[mid] <= i) lo = mid; else hi = mid - 1;
+        }
+        reinterpret_cast<int32_t*>(dst_ptrs[lo])[i - v_off[lo]] = src[i];
+    }
+}
+void launch_unpack_i32(int32_t count, const int32_t* v_off, const uint64_t* dst_ptrs, int32_t total,
+                       const int32_t* src, hipStream_t s) {
+    if (total > 0 && count > 0)
+        hipLaunchKernelGGL(k_unpack_i32, dim3(grid_for(total, 256, 16384)), dim3(256), 0, s, count, v_off, dst_ptrs,
+                           total, src);
 }
 
 // ---- CSR validation on the device (simple undirected graph, Sec. 2) ---------------------

@@ -939,6 +939,10 @@ struct SampledRun {
     uint32_t stream_id;
     bool early_stop = false;
     hipStream_t s;
+    // packed batches: per-vertex M (nullable; M is then the largest) and the
+    // vertex's id inside its own graph, from which its rank is drawn
+    const int32_t* Mv = nullptr;
+    const int32_t* lid = nullptr;
     Buf<uint8_t> alive, rank;
     Buf<int32_t> mark, rlist, wl, rc, lostmax, chA, chB, qv, qb, cursor, order;
     Buf<int64_t> d, core, ck, cs, cr, partials;
@@ -994,9 +998,9 @@ struct SampledRun {
             L.cap[i].alloc(ctx, n);
             L.off[i].alloc(ctx, (size_t)n + 1);
             if (i == 1)
-                launch_cap_level1(g->rp, n, M, L.cap[i].p, s);
+                launch_cap_level1(g->rp, n, M, Mv, L.cap[i].p, s);
             else
-                launch_cap_next(g->rp, g->col, n, M, L.cap[i - 1].p, L.cap[i].p, s);
+                launch_cap_next(g->rp, g->col, n, M, Mv, L.cap[i - 1].p, L.cap[i].p, s);
             launch_scan_i64(L.cap[i].p, L.off[i].p, n, partials.p, s);
             int64_t tot = 0;
             hip_ok(hipMemcpyAsync(&tot, L.off[i].p + n, 8, hipMemcpyDeviceToHost, s));
@@ -1017,18 +1021,19 @@ struct SampledRun {
 
     void init_lists() {
         const int32_t n = g->n;
-        launch_union1(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.view(1), nullptr, nullptr, st.p, s);
+        launch_union1(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.view(1), nullptr, nullptr, st.p,
+                      s);
         for (int i = 2; i <= h; ++i)
-            launch_union(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2, L.view(i - 1),
+            launch_union(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.hash_log2, L.view(i - 1),
                          L.view(i), cursor.p, order.p, nullptr, nullptr, st.p, s);
-        launch_estimate(nullptr, nullptr, n, alive.p, rank.p, L.size[h].p, L.kk[h].p, M, d.p, st.p, s);
+        launch_estimate(nullptr, nullptr, n, alive.p, rank.p, L.size[h].p, L.kk[h].p, M, Mv, d.p, st.p, s);
     }
 
     void setup(const uint8_t* alive_in) {
         alloc_common();
         init_state(st.p, s);
         launch_alive_from(alive_in, alive.p, g->n, s);
-        launch_ranks(rank.p, g->n, seed, stream_id, s);
+        launch_ranks(rank.p, g->n, seed, stream_id, s, lid);
         launch_fill_i32(mark.p, 0, g->n, s);
         launch_fill_i64(core.p, -1, g->n, s);
         launch_fill_i64(d.p, 0, g->n, s);
@@ -1066,15 +1071,15 @@ struct SampledRun {
                                         L.view(i - 1), L.view(i), lostmax.p, wl.p, &st.p->wl_count, st.p, q);
                     launch_classify(wl.p, &st.p->wl_count, L.view(i), lostmax.p, rc.p, &st.p->rc_count, q);
                     if (i == 1)
-                        launch_union1(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, L.view(1),
+                        launch_union1(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.view(1),
                                       changed[1], &st.p->changed_count[1], st.p, q);
                     else
-                        launch_union(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, L.hash_log2,
+                        launch_union(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.hash_log2,
                                      L.view(i - 1), L.view(i), cursor.p, order.p, changed[i & 1],
                                      &st.p->changed_count[i & 1], st.p, q, utimer);
                 }
                 launch_estimate(changed[h & 1], &st.p->changed_count[h & 1], n, alive.p, rank.p, L.size[h].p,
-                                L.kk[h].p, M, d.p, st.p, q);
+                                L.kk[h].p, M, Mv, d.p, st.p, q);
             }
         };
         const hipStream_t q = rp.prepare(caller, !graphs_off() && !ctx->prof_on, record);
@@ -1269,6 +1274,233 @@ extern "C" kh_status kh_core(kh_graph* g, const kh_params* P, int32_t* core_out,
         return KH_ENOMEM;
     }
     R->seconds = std::chrono::duration<double>(Clock::now() - t0).count();
+    return KH_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// batches: many graphs packed into one disjoint union
+// ---------------------------------------------------------------------------------------------
+// Components of a disjoint union never interact: N(v;h,X) stays inside v's
+// graph, so every h-degree, sample list and estimate of the union equals the
+// one of the graph alone, and the running-maximum peel of the union yields
+// each graph's own core numbers (Sec. 2's characterisation as the largest k
+// with a witness set containing v; a witness restricted to v's graph is still
+// one).  For the sampled path each vertex draws its rank from its id inside
+// its own graph and uses its own graph's M (Eq. (buffer) with that graph's n),
+// so the numbers are those of kh_core on the graph alone.
+namespace {
+
+struct Packed {
+    kh_graph G;
+    std::vector<int32_t> v_off;  // first vertex of each graph (count + 1 entries)
+    std::vector<int64_t> a_off;  // first arc of each graph
+    Buf<int32_t> lid, Mv;
+};
+
+void pack(kh_context* ctx, kh_graph* const* gs, int32_t count, Packed& P, bool sampled, const int32_t* Ms,
+          hipStream_t s) {
+    P.v_off.assign((size_t)count + 1, 0);
+    P.a_off.assign((size_t)count + 1, 0);
+    for (int32_t i = 0; i < count; ++i) {
+        P.v_off[i + 1] = P.v_off[i] + gs[i]->n;
+        P.a_off[i + 1] = P.a_off[i] + gs[i]->nnz;
+    }
+    const int32_t n = P.v_off[count];
+    const int64_t nnz = P.a_off[count];
+    kh_graph& G = P.G;
+    G.ctx = ctx;
+    G.n = n;
+    G.nnz = nnz;
+    G.h_rp.resize((size_t)n + 1);
+    for (int32_t i = 0; i < count; ++i) {
+        const int32_t* r = gs[i]->h_rp.data();
+        const int32_t a = (int32_t)P.a_off[i];
+        int32_t* dst = G.h_rp.data() + P.v_off[i];
+        for (int32_t v = 0; v < gs[i]->n; ++v) dst[v] = a + r[v];
+    }
+    G.h_rp[n] = (int32_t)nnz;
+    G.rp_own.alloc(ctx, (size_t)n + 1);
+    G.col_own.alloc(ctx, (size_t)std::max<int64_t>(nnz, 1));
+    hip_ok(hipMemcpyAsync(G.rp_own.p, G.h_rp.data(), 4 * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+    std::vector<uint64_t> cp((size_t)count);
+    for (int32_t i = 0; i < count; ++i) cp[i] = reinterpret_cast<uint64_t>(gs[i]->col);
+    Buf<int64_t> d_aoff;
+    Buf<int32_t> d_voff;
+    Buf<uint64_t> d_cp;
+    d_aoff.alloc(ctx, (size_t)count + 1);
+    d_voff.alloc(ctx, (size_t)count + 1);
+    d_cp.alloc(ctx, (size_t)count);
+    hip_ok(hipMemcpyAsync(d_aoff.p, P.a_off.data(), 8 * ((size_t)count + 1), hipMemcpyHostToDevice, s));
+    hip_ok(hipMemcpyAsync(d_voff.p, P.v_off.data(), 4 * ((size_t)count + 1), hipMemcpyHostToDevice, s));
+    hip_ok(hipMemcpyAsync(d_cp.p, cp.data(), 8 * (size_t)count, hipMemcpyHostToDevice, s));
+    launch_pack_col(count, d_aoff.p, d_voff.p, d_cp.p, nnz, G.col_own.p, s);
+    if (sampled) {
+        std::vector<int32_t> hl((size_t)n), hm((size_t)n);
+        for (int32_t i = 0; i < count; ++i)
+            for (int32_t v = 0; v < gs[i]->n; ++v) {
+                hl[(size_t)P.v_off[i] + v] = v;
+                hm[(size_t)P.v_off[i] + v] = Ms[i];
+            }
+        P.lid.alloc(ctx, n);
+        P.Mv.alloc(ctx, n);
+        hip_ok(hipMemcpyAsync(P.lid.p, hl.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s));
+        hip_ok(hipMemcpyAsync(P.Mv.p, hm.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s));
+    }
+    hip_ok(hipStreamSynchronize(s));  // the host tables above go out of scope
+    G.rp = G.rp_own.p;
+    G.col = G.col_own.p;
+}
+
+// One packed run over gs[0..count) (all with n > 0).
+void batch_chunk(kh_context* ctx, kh_graph* const* gs, int32_t count, const kh_params* P, int32_t* const* outs,
+                 kh_result* results, hipStream_t s) {
+    const auto t0 = Clock::now();
+    const bool sampled = P->epsilon > 0.0;
+    const bool out_dev = (P->flags & KH_OUT_DEVICE) != 0;
+    std::vector<int32_t> Ms((size_t)count, 0);
+    int32_t Mmax = 0;
+    if (sampled)
+        for (int32_t i = 0; i < count; ++i) {
+            Ms[i] = resolve_M(gs[i], P, false);
+            Mmax = std::max(Mmax, Ms[i]);
+        }
+    Packed PK;
+    pack(ctx, gs, count, PK, sampled, Ms.data(), s);
+    kh_graph* g = &PK.G;
+    const int32_t n = g->n;
+    const int h = effective_h(g, P->h);
+    ExactRun E;
+    SampledRun S;
+    const int64_t* core64 = nullptr;
+    RoundState fin{};
+    if (!sampled) {
+        E.g = g;
+        E.h = h;
+        E.s = s;
+        E.run_lazy();
+        core64 = E.core.p;
+        fin = E.fin;
+    } else {
+        S.g = g;
+        S.h = h;
+        S.M = Mmax;
+        S.Mv = PK.Mv.p;
+        S.lid = PK.lid.p;
+        S.seed = P->seed;
+        S.stream_id = 0;
+        S.s = s;
+        S.setup(nullptr);
+        S.peel(nullptr);
+        if (S.fin.overflow) fail(KH_EOVERFLOW);
+        core64 = S.core.p;
+        fin = S.fin;
+        for (auto& k : S.L.keys) k.release();
+    }
+    Buf<int32_t> c32;
+    c32.alloc(ctx, n);
+    finish_core(ctx, core64, n, c32.p, true, s, nullptr);
+    std::vector<int32_t> hc((size_t)n);
+    hip_ok(hipMemcpyAsync(hc.data(), c32.p, 4 * (size_t)n, hipMemcpyDeviceToHost, s));
+    if (out_dev) {
+        std::vector<uint64_t> dp((size_t)count);
+        for (int32_t i = 0; i < count; ++i) dp[i] = reinterpret_cast<uint64_t>(outs[i]);
+        Buf<int32_t> d_voff;
+        Buf<uint64_t> d_dp;
+        d_voff.alloc(ctx, (size_t)count + 1);
+        d_dp.alloc(ctx, (size_t)count);
+        hip_ok(hipMemcpyAsync(d_voff.p, PK.v_off.data(), 4 * ((size_t)count + 1), hipMemcpyHostToDevice, s));
+        hip_ok(hipMemcpyAsync(d_dp.p, dp.data(), 8 * (size_t)count, hipMemcpyHostToDevice, s));
+        launch_unpack_i32(count, d_voff.p, d_dp.p, n, c32.p, s);
+        hip_ok(hipStreamSynchronize(s));
+    } else {
+        hip_ok(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < count; ++i)
+            std::memcpy(outs[i], hc.data() + PK.v_off[i], 4 * (size_t)gs[i]->n);
+    }
+    const double secs = std::chrono::duration<double>(Clock::now() - t0).count();
+    for (int32_t i = 0; i < count; ++i) {
+        if (!results) break;
+        kh_result* R = &results[i];
+        int32_t m = 0;
+        for (int32_t v = PK.v_off[i]; v < PK.v_off[i + 1]; ++v) m = std::max(m, hc[v]);
+        R->max_core = m;
+        R->M_used = Ms[i];
+        R->rounds = fin.rounds;
+        R->edges_traversed = (int64_t)fin.te;
+        R->arcs_scanned = (int64_t)fin.arcs;
+        R->list_elements = (int64_t)fin.elems;
+        R->seconds = secs;
+    }
+    prof_add_counters(ctx, fin);
+    if (results && (P->flags & KH_WANT_DENSE)) {
+        // the densest core is a per-graph quantity: one pass per graph over its
+        // slice of the packed core map
+        for (int32_t i = 0; i < count; ++i) {
+            const int64_t* slice = core64 + PK.v_off[i];
+            if (sampled) dense_sampled(gs[i], P, slice, results[i].max_core, &results[i], s);
+            else dense_exact(gs[i], P, slice, results[i].max_core, &results[i], s);
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" kh_status kh_core_batch(kh_context* ctx, int32_t count, kh_graph* const* graphs, const kh_params* P,
+                                   int32_t* const* core_outs, kh_result* results, void* stream) {
+    try {
+        if (!ctx || count < 0 || (count > 0 && (!graphs || !core_outs))) fail(KH_EINVAL);
+        if (count == 0) return KH_OK;
+        for (int32_t i = 0; i < count; ++i) {
+            check_params(graphs[i], P);
+            if (graphs[i]->ctx != ctx) fail(KH_EINVAL);
+            if (graphs[i]->n > 0 && !core_outs[i]) fail(KH_EINVAL);
+            if (results) clear_result(&results[i]);
+        }
+        if (P->flags & KH_EARLY_STOP) fail(KH_ENOTIMPL);
+        hip_ok(hipSetDevice(ctx->device));
+        auto s = static_cast<hipStream_t>(stream);
+        const bool sampled = P->epsilon > 0.0;
+        // chunks of consecutive non-empty graphs: packed ids and arc offsets stay
+        // in int32, sampled keys hold 24-bit ids
+        int64_t vmax = sampled ? (int64_t)kMaxSampledN : (int64_t)INT32_MAX - 1;
+        // KH_BATCH_MAX_VERTICES (tests): smaller unions
+        if (const char* e = std::getenv("KH_BATCH_MAX_VERTICES")) {
+            const long long x = std::atoll(e);
+            if (x > 0) vmax = std::min<int64_t>(vmax, x);
+        }
+        std::vector<kh_graph*> cg;
+        std::vector<int32_t*> co;
+        std::vector<int32_t> ci;
+        int64_t vn = 0, an = 0;
+        auto flush = [&]() {
+            if (cg.empty()) return;
+            std::vector<kh_result> rs(cg.size());
+            for (auto& r : rs) clear_result(&r);
+            batch_chunk(ctx, cg.data(), (int32_t)cg.size(), P, co.data(), results ? rs.data() : nullptr, s);
+            if (results)
+                for (size_t j = 0; j < cg.size(); ++j) results[ci[j]] = rs[j];
+            cg.clear();
+            co.clear();
+            ci.clear();
+            vn = an = 0;
+        };
+        for (int32_t i = 0; i < count; ++i) {
+            kh_graph* g = graphs[i];
+            if (g->n == 0) continue;
+            if (sampled && g->n > kMaxSampledN) fail(KH_ENOTIMPL);
+            if (vn + g->n > vmax || an + g->nnz > (int64_t)INT32_MAX) flush();
+            cg.push_back(g);
+            co.push_back(core_outs[i]);
+            ci.push_back(i);
+            vn += g->n;
+            an += g->nnz;
+        }
+        flush();
+    } catch (const KhError& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        return KH_ENOMEM;
+    }
     return KH_OK;
 }
 

@@ -73,7 +73,16 @@ struct PullTimer {
 
 // ---- kernels: graph, ranks, bookkeeping (kh_graph.hip) -------------------------------
 
-void launch_ranks(uint8_t* r, int32_t n, uint64_t seed, uint32_t stream_id, hipStream_t s);
+// lid (nullable): rank of vertex v is drawn for id lid[v] (the vertex's id in its own graph).
+void launch_ranks(uint8_t* r, int32_t n, uint64_t seed, uint32_t stream_id, hipStream_t s,
+                  const int32_t* lid = nullptr);
+// Pack graphs into one disjoint union: col[a_off[g] + j] = cols[g][j] + v_off[g].
+void launch_pack_col(int32_t count, const int64_t* a_off, const int32_t* v_off, const uint64_t* col_ptrs,
+                     int64_t nnz, int32_t* col, hipStream_t s);
+// Scatter a packed int32 vector back to per-graph device arrays (graphs with
+// n = 0 must be left out of the tables: v_off is strictly increasing).
+void launch_unpack_i32(int32_t count, const int32_t* v_off, const uint64_t* dst_ptrs, int32_t total,
+                       const int32_t* src, hipStream_t s);
 void launch_validate(const int32_t* rp, const int32_t* col, int32_t n, int64_t nnz, int* err, hipStream_t s);
 void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
@@ -197,18 +206,19 @@ struct LevelView {
     uint32_t* meta;      // packed |B[v,i]| (bits 0-15) | k[v,i] (16-23) | rank of the first entry (24-31)
 };
 
-void launch_cap_level1(const int32_t* rp, int32_t n, int32_t M, int64_t* cap, hipStream_t s);
-void launch_cap_next(const int32_t* rp, const int32_t* col, int32_t n, int32_t M, const int64_t* cap_prev,
-                     int64_t* cap, hipStream_t s);
+// Mv (nullable): per-vertex M, for batches of graphs of different sizes.
+void launch_cap_level1(const int32_t* rp, int32_t n, int32_t M, const int32_t* Mv, int64_t* cap, hipStream_t s);
+void launch_cap_next(const int32_t* rp, const int32_t* col, int32_t n, int32_t M, const int32_t* Mv,
+                     const int64_t* cap_prev, int64_t* cap, hipStream_t s);
 // Level 1 (neighbour lists are singletons).  worklist == NULL: all vertices (initialisation).
 void launch_union1(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
-                   const uint8_t* alive, const uint8_t* rank, int32_t M, LevelView cur, int32_t* changed,
-                   int* changed_count, RoundState* st, hipStream_t s);
+                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, LevelView cur,
+                   int32_t* changed, int* changed_count, RoundState* st, hipStream_t s);
 // Level i >= 2.
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
-                  const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, LevelView prev, LevelView cur,
-                  int32_t* cursor, int32_t* order, int32_t* changed, int* changed_count, RoundState* st,
-                  hipStream_t s, PullTimer* timer = nullptr);
+                  const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, int hash_log2,
+                  LevelView prev, LevelView cur, int32_t* cursor, int32_t* order, int32_t* changed,
+                  int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer = nullptr);
 // Propagate the deletions and changes of level i-1 over the arcs of the queued
 // vertices: mark + append alive neighbours, fold the highest lost rank into
 // lostmax[], and keep m[.,i] current.
@@ -221,7 +231,7 @@ void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int3
                      int* rc_count, hipStream_t s);
 // Alg. 1 estimate from level h.  worklist == NULL: all vertices.
 void launch_estimate(const int32_t* worklist, const int* wl_count, int32_t n, const uint8_t* alive,
-                     const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, int64_t* d,
-                     RoundState* st, hipStream_t s);
+                     const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, const int32_t* Mv,
+                     int64_t* d, RoundState* st, hipStream_t s);
 
 }  // namespace kh

@@ -31,23 +31,27 @@ __device__ __forceinline__ int meta_size(uint32_t m) { return (int)(m & 0xFFFFu)
 __device__ __forceinline__ int meta_k(uint32_t m) { return (int)((m >> 16) & 0xFFu); }
 __device__ __forceinline__ int meta_head(uint32_t m) { return (int)(m >> 24); }
 
-__global__ void k_cap_level1(const int32_t* __restrict__ rp, int32_t n, int32_t M, int64_t* __restrict__ cap) {
+__global__ void k_cap_level1(const int32_t* __restrict__ rp, int32_t n, int32_t M, const int32_t* __restrict__ Mv,
+                             int64_t* __restrict__ cap) {
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int64_t Mx = Mv ? Mv[v] : M;
         const int64_t c = 1 + (int64_t)(rp[v + 1] - rp[v]);
-        cap[v] = c < M ? c : M;
+        cap[v] = c < Mx ? c : Mx;
     }
 }
-void launch_cap_level1(const int32_t* rp, int32_t n, int32_t M, int64_t* cap, hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_cap_level1, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, rp, n, M, cap);
+void launch_cap_level1(const int32_t* rp, int32_t n, int32_t M, const int32_t* Mv, int64_t* cap, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_cap_level1, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, rp, n, M, Mv, cap);
 }
 
 // cap_i(v) = min(M, 1 + sum_w cap_{i-1}(w)) bounds |B[v,i]| for every X.
-__global__ void k_cap_next(const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t n, int32_t M,
-                           const int64_t* __restrict__ cap_prev, int64_t* __restrict__ cap) {
+__global__ void k_cap_next(const int32_t* __restrict__ rp, const int32_t* __restrict__ col, int32_t n, int32_t M0,
+                           const int32_t* __restrict__ Mv, const int64_t* __restrict__ cap_prev,
+                           int64_t* __restrict__ cap) {
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int l = lane_id();
     for (int32_t v = wave; v < n; v += nwaves) {
+        const long long M = Mv ? Mv[v] : M0;
         long long sum = 0;
         for (int32_t p = rp[v] + l; p < rp[v + 1]; p += 64) {
             sum += cap_prev[col[p]];
@@ -60,11 +64,11 @@ __global__ void k_cap_next(const int32_t* __restrict__ rp, const int32_t* __rest
         }
     }
 }
-void launch_cap_next(const int32_t* rp, const int32_t* col, int32_t n, int32_t M, const int64_t* cap_prev,
-                     int64_t* cap, hipStream_t s) {
+void launch_cap_next(const int32_t* rp, const int32_t* col, int32_t n, int32_t M, const int32_t* Mv,
+                     const int64_t* cap_prev, int64_t* cap, hipStream_t s) {
     if (n > 0)
         hipLaunchKernelGGL(k_cap_next, dim3(grid_for((int64_t)n * 64, 256, 16384)), dim3(256), 0, s, rp, col, n, M,
-                           cap_prev, cap);
+                           Mv, cap_prev, cap);
 }
 
 // ---- level 1: T = {v} + alive neighbours (all distinct) -------------------------------------
@@ -74,8 +78,8 @@ void launch_cap_next(const int32_t* rp, const int32_t* col, int32_t n, int32_t M
 __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ worklist, const int* wl_count, int32_t n,
                                                 const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                 const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
-                                                int32_t M, LevelView cur, int32_t* __restrict__ changed,
-                                                int* changed_count, RoundState* st) {
+                                                int32_t M0, const int32_t* __restrict__ Mv, LevelView cur,
+                                                int32_t* __restrict__ changed, int* changed_count, RoundState* st) {
     __shared__ int hist[256];
     __shared__ int s_k, s_size, s_nb, s_ok, s_os, s_lost, s_head;
     const int tid = threadIdx.x;
@@ -84,6 +88,7 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
     for (int wi = blockIdx.x; wi < total; wi += gridDim.x) {
         const int32_t v = worklist ? worklist[wi] : wi;
         if (!alive[v]) continue;
+        const int M = Mv ? Mv[v] : M0;
         const int32_t b = rp[v], e = rp[v + 1];
         hist[tid] = 0;
         if (tid == 0) {
@@ -165,11 +170,11 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
 }
 
 void launch_union1(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
-                   const uint8_t* alive, const uint8_t* rank, int32_t M, LevelView cur, int32_t* changed,
-                   int* changed_count, RoundState* st, hipStream_t s) {
+                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, LevelView cur,
+                   int32_t* changed, int* changed_count, RoundState* st, hipStream_t s) {
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
-    hipLaunchKernelGGL(k_union1, dim3(grid), dim3(256), 0, s, worklist, wl_count, n, rp, col, alive, rank, M, cur,
+    hipLaunchKernelGGL(k_union1, dim3(grid), dim3(256), 0, s, worklist, wl_count, n, rp, col, alive, rank, M, Mv, cur,
                        changed, changed_count, st);
 }
 
@@ -339,9 +344,10 @@ __device__ void union_pass_wide(int lo, int32_t b, int32_t span, bool hub, const
 __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ worklist, const int* wl_count, int32_t n,
                                                const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
-                                               int32_t M, int hash_log2, LevelView prev, LevelView cur,
-                                               int32_t* __restrict__ cursor, int32_t* __restrict__ order,
-                                               int32_t* __restrict__ changed, int* changed_count, RoundState* st) {
+                                               int32_t M0, const int32_t* __restrict__ Mv, int hash_log2,
+                                               LevelView prev, LevelView cur, int32_t* __restrict__ cursor,
+                                               int32_t* __restrict__ order, int32_t* __restrict__ changed,
+                                               int* changed_count, RoundState* st) {
     extern __shared__ uint32_t tab[];
     __shared__ int hist[256];
     __shared__ int hk[256];
@@ -353,12 +359,14 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
     const int tid = threadIdx.x;
     const int bs = blockDim.x;
     const int hcap = 1 << hash_log2;
-    HashSet H{tab, (uint32_t)(hcap - 1), 32 - hash_log2, &s_count, hist, M};
+    HashSet H{tab, (uint32_t)(hcap - 1), 32 - hash_log2, &s_count, hist, M0};
     const int total = worklist ? *wl_count : n;
     unsigned long long elems = 0, bytes = 0;
     for (int wi = blockIdx.x; wi < total; wi += gridDim.x) {
         const int32_t v = worklist ? worklist[wi] : wi;
         if (!alive[v]) continue;
+        const int M = Mv ? Mv[v] : M0;
+        H.M = M;
         const int32_t b = rp[v], e = rp[v + 1];
         const int32_t deg = e - b;
         if (tid == 0) bytes += 8 + 6;  // rp[v], rank/alive/old state of v
@@ -529,9 +537,9 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
 }
 
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
-                  const uint8_t* alive, const uint8_t* rank, int32_t M, int hash_log2, LevelView prev, LevelView cur,
-                  int32_t* cursor, int32_t* order, int32_t* changed, int* changed_count, RoundState* st,
-                  hipStream_t s, PullTimer* timer) {
+                  const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, int hash_log2,
+                  LevelView prev, LevelView cur, int32_t* cursor, int32_t* order, int32_t* changed,
+                  int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer) {
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
     const size_t lds = sizeof(uint32_t) << hash_log2;
@@ -543,7 +551,7 @@ void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const
     const bool timed = timer && timer->used < timer->cap;
     if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
     hipLaunchKernelGGL(k_union, dim3(grid), dim3(kUnionThreads), lds, s, worklist, wl_count, n, rp, col, alive, rank,
-                       M, hash_log2, prev, cur, cursor, order, changed, changed_count, st);
+                       M, Mv, hash_log2, prev, cur, cursor, order, changed, changed_count, st);
     if (timed) {
         (void)hipEventRecord(timer->ev[2 * timer->used + 1], s);
         timer->used += 1;
@@ -644,13 +652,14 @@ void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int3
 // ---- Alg. 1: d = |B[v,h] \ {v}| 2^k, and max(d, M 2^(k-1)) when k > 0 ---------------------------
 __global__ void k_estimate(const int32_t* __restrict__ worklist, const int* wl_count, int32_t n,
                            const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
-                           const int32_t* __restrict__ size, const uint8_t* __restrict__ kk, int32_t M,
-                           int64_t* __restrict__ d, RoundState* st) {
+                           const int32_t* __restrict__ size, const uint8_t* __restrict__ kk, int32_t M0,
+                           const int32_t* __restrict__ Mv, int64_t* __restrict__ d, RoundState* st) {
     const int total = worklist ? *wl_count : n;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         const int32_t v = worklist ? worklist[i] : i;
         if (!alive[v]) continue;
         const int k = kk[v];
+        const long long M = Mv ? Mv[v] : M0;
         const long long T = (long long)size[v] - (rank[v] >= k ? 1 : 0);
         long long est;
         if (k >= 62 || (T > 0 && T > (LLONG_MAX >> k))) {
@@ -659,7 +668,7 @@ __global__ void k_estimate(const int32_t* __restrict__ worklist, const int* wl_c
         } else {
             est = T << k;
             if (k > 0) {
-                const long long fl = (long long)M << (k - 1);
+                const long long fl = M << (k - 1);
                 est = fl > est ? fl : est;
             }
         }
@@ -667,12 +676,12 @@ __global__ void k_estimate(const int32_t* __restrict__ worklist, const int* wl_c
     }
 }
 void launch_estimate(const int32_t* worklist, const int* wl_count, int32_t n, const uint8_t* alive,
-                     const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, int64_t* d,
-                     RoundState* st, hipStream_t s) {
+                     const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, const int32_t* Mv,
+                     int64_t* d, RoundState* st, hipStream_t s) {
     if (n <= 0) return;
     const int grid = worklist ? 1024 : grid_for(n, 256, 8192);
-    hipLaunchKernelGGL(k_estimate, dim3(grid), dim3(256), 0, s, worklist, wl_count, n, alive, rank, size, kk, M, d,
-                       st);
+    hipLaunchKernelGGL(k_estimate, dim3(grid), dim3(256), 0, s, worklist, wl_count, n, alive, rank, size, kk, M, Mv,
+                       d, st);
 }
 
 }  // namespace kh

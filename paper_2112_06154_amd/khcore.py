@@ -37,7 +37,8 @@ KH_OUT_DEVICE = 8
 
 EXPORTED = [
     "kh_status_str", "kh_buffer_size", "kh_validate_csr", "kh_context_create", "kh_context_destroy",
-    "kh_graph_load_csr", "kh_graph_free", "kh_graph_n", "kh_graph_nnz", "kh_core", "kh_hdeg", "kh_ranks",
+    "kh_graph_load_csr", "kh_graph_free", "kh_graph_n", "kh_graph_nnz", "kh_core", "kh_core_batch", "kh_hdeg",
+    "kh_ranks",
     "kh_sampled_lists", "kh_dense", "kh_profile_enable", "kh_profile_read",
 ]
 
@@ -96,6 +97,8 @@ def lib():
         L.kh_graph_nnz.restype = i64
         L.kh_core.argtypes = [P, ctypes.POINTER(Params), P, ctypes.POINTER(Result), P]
         L.kh_core.restype = i32
+        L.kh_core_batch.argtypes = [P, i32, P, ctypes.POINTER(Params), P, P, P]
+        L.kh_core_batch.restype = i32
         L.kh_hdeg.argtypes = [P, i32, P, u32, P, ctypes.POINTER(i64), P]
         L.kh_hdeg.restype = i32
         L.kh_ranks.argtypes = [P, i32, u64, u32, P, P]
@@ -258,6 +261,29 @@ def core(graph: Graph, h: int, epsilon: float = 0.0, out=None, stream=None, **kw
     if isinstance(out, np.ndarray):
         out = out[:graph.n]
     return out, res.as_dict()
+
+
+def core_batch(graphs, h: int, epsilon: float = 0.0, outs=None, stream=None, **kw):
+    """kh_core over many graphs packed into disjoint unions (kh_core_batch).
+
+    Returns (list of core arrays, list of result dicts).  `outs` may be a list
+    of int32 torch device tensors (one per graph), in which case the numbers
+    stay on the device."""
+    graphs = list(graphs)
+    count = len(graphs)
+    if count == 0:
+        return [], []
+    p = make_params(h, epsilon, out_device=outs is not None, **kw)
+    if outs is None:
+        outs = [np.zeros(max(g.n, 1), np.int32) for g in graphs]
+    handles = (ctypes.c_void_p * max(count, 1))(*[g.handle for g in graphs])
+    optrs = (ctypes.c_void_p * max(count, 1))(*[_ptr(o) for o in outs])
+    res = (Result * max(count, 1))()
+    ctx = graphs[0].ctx.handle
+    _check(lib().kh_core_batch(ctx, count, handles, ctypes.byref(p), optrs, res, _stream(stream)),
+           "kh_core_batch")
+    cores = [o[:g.n] if isinstance(o, np.ndarray) else o for o, g in zip(outs, graphs)]
+    return cores, [res[i].as_dict() for i in range(count)]
 
 
 def hdeg(graph: Graph, h: int, alive=None, out=None, stream=None):
