@@ -682,8 +682,10 @@ __device__ __forceinline__ long long cur_level(const RoundState* st) {
 }
 
 // hist[b] = inexact alive vertices with bound - c' in bucket b (c' = max(c, min)).
+// shist (nullable, packed unions): the same per segment, shist[seg * 48 + b].
 __global__ void k_bound_hist(const uint8_t* __restrict__ alive, const int64_t* __restrict__ deg,
-                             const uint8_t* __restrict__ exact, int32_t n, RoundState* st) {
+                             const uint8_t* __restrict__ exact, int32_t n, RoundState* st,
+                             const int32_t* __restrict__ seg, int* __restrict__ shist) {
     __shared__ int h[48];
     if (threadIdx.x < 48) h[threadIdx.x] = 0;
     __syncthreads();
@@ -694,6 +696,7 @@ __global__ void k_bound_hist(const uint8_t* __restrict__ alive, const int64_t* _
                 const long long d = deg[v] - c;
                 const int b = d <= 0 ? 0 : min(47, 64 - __clzll((unsigned long long)d));
                 atomicAdd(&h[b], 1);
+                if (shist) atomicAdd(&shist[(size_t)seg[v] * 48 + b], 1);
             }
         }
     }
@@ -701,9 +704,40 @@ __global__ void k_bound_hist(const uint8_t* __restrict__ alive, const int64_t* _
     if (threadIdx.x < 48 && h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
 }
 void launch_bound_hist(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
-                       hipStream_t s) {
+                       hipStream_t s, const int32_t* seg, int* shist) {
     if (n > 0)
-        hipLaunchKernelGGL(k_bound_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, alive, deg, exact, n, st);
+        hipLaunchKernelGGL(k_bound_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, alive, deg, exact, n, st, seg,
+                           shist);
+}
+
+// Per segment of a packed union: the bound threshold of its next sources, chosen
+// as k_decide does for one graph (whole buckets, up to cap sources, at least
+// every one at or below c'); segments with nothing at or below c' take no
+// sources.  Zeroes the segment histograms for the next iteration.
+__global__ void k_decide_seg(RoundState* st, int nseg, int* __restrict__ shist, long long* __restrict__ shi, int cap) {
+    const bool rec = st->mode == 1;
+    const long long c = cur_level(st);
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < nseg; g += gridDim.x * blockDim.x) {
+        int* hg = shist + (size_t)g * 48;
+        if (rec) {
+            long long hi = LLONG_MIN;
+            if (hg[0] > 0) {
+                int acc = hg[0], B = 0;
+                for (int b = 1; b < 48; ++b) {
+                    if (acc + hg[b] > cap) break;
+                    acc += hg[b];
+                    B = b;
+                }
+                hi = B == 0 ? c : c + ((1ll << B) - 1);
+            }
+            shi[g] = hi;
+        }
+        for (int b = 0; b < 48; ++b)
+            if (hg[b]) hg[b] = 0;
+    }
+}
+void launch_decide_seg(RoundState* st, int nseg, int* shist, long long* shi, int cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide_seg, dim3(grid_for(nseg, 256, 1024)), dim3(256), 0, s, st, nseg, shist, shi, cap);
 }
 
 // Commit the round when no inexact vertex is at or below c'; otherwise recompute
@@ -733,25 +767,38 @@ void launch_decide(RoundState* st, int cap, hipStream_t s) {
 
 __global__ void k_pick(const uint8_t* __restrict__ alive, const int64_t* __restrict__ deg,
                        const uint8_t* __restrict__ exact, int32_t n, RoundState* st, int32_t* __restrict__ out,
-                       int cap) {
+                       int cap, const int32_t* __restrict__ seg, int* __restrict__ gcnt, int32_t* __restrict__ sbit,
+                       int qbits, const long long* __restrict__ shi) {
     if (st->mode != 1) return;
-    const long long hi = st->hi;
+    const long long hi0 = st->hi;
     const int32_t stride = gridDim.x * blockDim.x;
     for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
         if (*(volatile int*)&st->rc_count >= cap) break;
         const int32_t v = base + threadIdx.x;
-        const bool want = v < n && alive[v] && !exact[v] && deg[v] <= hi;
+        bool want = v < n && alive[v] && !exact[v];
+        if (want) want = deg[v] <= (shi ? shi[seg[v]] : hi0);
+        int b = 0;
+        if (want && seg) {
+            // a bit position of its own graph; the rest waits for a later batch
+            b = atomicAdd(&gcnt[seg[v]], 1);
+            want = b < qbits;
+        }
         const int slot = wave_append_slot(want, &st->rc_count);
-        if (want && slot < cap) out[slot] = v;
+        if (want && slot < cap) {
+            out[slot] = v;
+            if (sbit) sbit[slot] = b;
+        }
     }
 }
 __global__ void k_pick_finish(RoundState* st, int cap) {
     if (st->mode == 1) st->ms_ns = st->rc_count < cap ? st->rc_count : cap;
 }
 void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
-                 int32_t* out, int cap, hipStream_t s) {
+                 int32_t* out, int cap, hipStream_t s, const int32_t* seg, int* gcnt, int32_t* sbit, int qbits,
+                 const long long* shi) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_pick, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, alive, deg, exact, n, st, out, cap);
+    hipLaunchKernelGGL(k_pick, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, alive, deg, exact, n, st, out, cap, seg,
+                       gcnt, sbit, qbits, shi);
     hipLaunchKernelGGL(k_pick_finish, dim3(1), dim3(1), 0, s, st, cap);
 }
 

@@ -137,7 +137,11 @@ struct kh_graph {
     std::vector<int32_t> h_rp;
     // work items of the h-degree pull kernel (built on first use)
     bool items_built = false;
-    Buf<int32_t> it_u, it_beg, it_end, split_list;
+    Buf<int32_t> it_u, it_beg, it_end, split_list, vitem;
+    // packed unions of several graphs: segment (graph) of every vertex
+    Buf<int32_t> seg_own;
+    const int32_t* seg = nullptr;
+    int32_t nseg = 1;
     Buf<uint8_t> it_split;
     MsItems items{};
 };
@@ -440,7 +444,7 @@ void build_items(kh_graph* g, hipStream_t s) {
     if (g->items_built) return;
     const int32_t n = g->n;
     const std::vector<int32_t>& rp = g->h_rp;
-    std::vector<int32_t> iu, ib, ie, sl;
+    std::vector<int32_t> iu, ib, ie, sl, vit((size_t)std::max(n, 1), -1);
     std::vector<uint8_t> isp;
     int32_t maxd = 0;
     for (int32_t v = 0; v < n; ++v) maxd = std::max(maxd, rp[v + 1] - rp[v]);
@@ -448,6 +452,7 @@ void build_items(kh_graph* g, hipStream_t s) {
         const int32_t d = rp[v + 1] - rp[v];
         if (d > kPullChunk) {
             sl.push_back(v);
+            vit[v] = (int32_t)iu.size();
             for (int32_t b = rp[v]; b < rp[v + 1]; b += kPullChunk) {
                 iu.push_back(v);
                 ib.push_back(b);
@@ -477,6 +482,7 @@ void build_items(kh_graph* g, hipStream_t s) {
         const int32_t d = rp[v + 1] - rp[v];
         if (d >= 1 && d <= kPullChunk) {
             const size_t at = base + (size_t)start[(size_t)d]++;
+            vit[v] = (int32_t)at;
             iu[at] = v;
             ib[at] = rp[v];
             ie[at] = rp[v + 1];
@@ -489,6 +495,8 @@ void build_items(kh_graph* g, hipStream_t s) {
     g->it_end.alloc(ctx, ni);
     g->it_split.alloc(ctx, ni);
     g->split_list.alloc(ctx, sl.size());
+    g->vitem.alloc(ctx, vit.size());
+    hip_ok(hipMemcpyAsync(g->vitem.p, vit.data(), vit.size() * 4, hipMemcpyHostToDevice, s));
     if (ni) {
         hip_ok(hipMemcpyAsync(g->it_u.p, iu.data(), ni * 4, hipMemcpyHostToDevice, s));
         hip_ok(hipMemcpyAsync(g->it_beg.p, ib.data(), ni * 4, hipMemcpyHostToDevice, s));
@@ -504,6 +512,8 @@ void build_items(kh_graph* g, hipStream_t s) {
     g->items.split = g->it_split.p;
     g->items.nsplit = (int32_t)sl.size();
     g->items.split_list = g->split_list.p;
+    g->items.vitem = g->vitem.p;
+    g->items.nnz = g->nnz;
     g->items_built = true;
 }
 
@@ -516,14 +526,24 @@ int pick_q(int64_t sources) {
 
 struct Planes {
     Buf<uint64_t> vis, frA, frB, acc, valid;
-    Buf<uint32_t> bmA, bmB, bmT, cnt;
-    Buf<int32_t> touched;
-    Buf<int> tcount;
+    Buf<uint32_t> bmA, bmB, bmT, bmC, bmTile, cnt;
+    Buf<int32_t> touched, flA, flB, tl, cvA, cvB, ciA, ciB, sbit;
+    Buf<int> tcount, gcnt;
+    Buf<int2> fcA, fcB;
+    Buf<MsCtl> ctl;
     int qmax = 0;
-    void alloc(kh_context* ctx, int32_t n, int qmax_) {
+    const int32_t* seg = nullptr;
+    int32_t ns_cap = 0;
+    // nitems: work items of the graph (build_items first).  seg/nseg: segments
+    // of a packed union (seg == NULL: one graph).
+    void alloc(kh_context* ctx, int32_t n, int64_t nnz, int qmax_, int32_t nitems, const int32_t* seg_ = nullptr,
+               int32_t nseg = 1) {
         qmax = qmax_;
-        const size_t words = (size_t)std::max(n, 1) * qmax;
-        const size_t bm = ((size_t)std::max(n, 1) + 31) / 32;
+        seg = seg_;
+        const size_t nn = (size_t)std::max(n, 1);
+        const size_t words = nn * qmax;
+        const size_t bm = (nn + 31) / 32;
+        const size_t ntiles = (nn + 63) / 64;
         vis.alloc(ctx, words);
         frA.alloc(ctx, words);
         frB.alloc(ctx, words);
@@ -532,14 +552,37 @@ struct Planes {
         bmA.alloc(ctx, bm);
         bmB.alloc(ctx, bm);
         bmT.alloc(ctx, bm);
-        cnt.alloc(ctx, 64 * 16);
-        touched.alloc(ctx, (size_t)std::max(n, 1));
+        bmC.alloc(ctx, bm);
+        bmTile.alloc(ctx, (ntiles + 31) / 32);
+        cnt.alloc(ctx, (size_t)64 * std::max(qmax, 16) * (seg ? (size_t)std::max(nseg, 1) : 1));
+        touched.alloc(ctx, nn);
+        flA.alloc(ctx, nn);
+        flB.alloc(ctx, nn);
+        fcA.alloc(ctx, nn + (size_t)(nnz / 64) + 1);
+        fcB.alloc(ctx, nn + (size_t)(nnz / 64) + 1);
+        tl.alloc(ctx, ntiles);
+        if (seg) {
+            sbit.alloc(ctx, nn);
+            gcnt.alloc(ctx, (size_t)std::max(nseg, 1));
+            ns_cap = (int32_t)nn;
+        }
+        cvA.alloc(ctx, nn);
+        cvB.alloc(ctx, nn);
+        ciA.alloc(ctx, (size_t)std::max(nitems, 1));
+        ciB.alloc(ctx, (size_t)std::max(nitems, 1));
         tcount.alloc(ctx, 1);
+        ctl.alloc(ctx, 1);
     }
+    // the planes, bitmaps, counters and control block start all-zero; every
+    // batch leaves them so
     void clear(hipStream_t s) {
         hip_ok(hipMemsetAsync(vis.p, 0, vis.count * 8, s));
         hip_ok(hipMemsetAsync(acc.p, 0, acc.count * 8, s));
         hip_ok(hipMemsetAsync(cnt.p, 0, cnt.count * 4, s));
+        for (Buf<uint32_t>* b : {&bmA, &bmB, &bmT, &bmC, &bmTile}) hip_ok(hipMemsetAsync(b->p, 0, b->count * 4, s));
+        hip_ok(hipMemsetAsync(tcount.p, 0, sizeof(int), s));
+        hip_ok(hipMemsetAsync(ctl.p, 0, sizeof(MsCtl), s));
+        if (gcnt.p) hip_ok(hipMemsetAsync(gcnt.p, 0, gcnt.count * sizeof(int), s));
     }
     PullTimer* timer = nullptr;
     MsPlanes view(int q) const {
@@ -553,8 +596,24 @@ struct Planes {
         P.bmA = bmA.p;
         P.bmB = bmB.p;
         P.bmT = bmT.p;
+        P.bmC = bmC.p;
         P.touched = touched.p;
         P.touched_count = tcount.p;
+        P.flA = flA.p;
+        P.flB = flB.p;
+        P.fcA = fcA.p;
+        P.fcB = fcB.p;
+        P.tl = tl.p;
+        P.bmTile = bmTile.p;
+        P.seg = seg;
+        P.sbit = seg ? sbit.p : nullptr;
+        P.gcnt = seg ? gcnt.p : nullptr;
+        P.ns_cap = seg ? ns_cap : 64 * q;
+        P.cvA = cvA.p;
+        P.cvB = cvB.p;
+        P.ciA = ciA.p;
+        P.ciB = ciB.p;
+        P.ctl = ctl.p;
         P.cnt = cnt.p;
         P.valid = valid.p;
         return P;
@@ -572,7 +631,12 @@ void hdeg_sources(kh_graph* g, Planes& PL, const uint8_t* alive, const int32_t* 
         const int64_t rest = count - done;
         const int q = std::min(PL.qmax, pick_q(rest));
         const int ns = (int)std::min<int64_t>(rest, 64ll * q);
-        ms_batch(PL.view(q), g->items, g->n, g->rp, g->col, alive, adeg, src + done, ns, nullptr, h, deg, st, s);
+        MsPlanes P = PL.view(q);
+        P.seg = nullptr;  // host-chosen batches number their sources 0..ns-1
+        P.sbit = nullptr;
+        P.gcnt = nullptr;
+        P.ns_cap = 64 * q;
+        ms_batch(P, g->items, g->n, g->rp, g->col, alive, adeg, src + done, ns, nullptr, h, deg, st, s);
         done += ns;
     }
 }
@@ -708,7 +772,7 @@ struct ExactRun {
         cs.alloc(ctx, (size_t)n + 1);
         cr.alloc(ctx, (size_t)n + 1);
         st.alloc(ctx, 1);
-        PL.alloc(ctx, n, pick_q(n));
+        PL.alloc(ctx, n, g->nnz, pick_q(n), g->items.nitems, g->seg, g->nseg);
         PL.clear(s);
         init_state(st.p, s);
     }
@@ -802,7 +866,16 @@ struct ExactRun {
         launch_anchor(nullptr, nullptr, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 0, s);
         launch_lower_bound(nullptr, nullptr, n, h, alive.p, adeg.p, anchor.p, deg.p, exact.p, s);
         long long iters = 0;
-        const int cap = 64 * PL.qmax;
+        // one batch takes up to 64 Q sources, per graph of a packed union
+        const int qbits = 64 * PL.qmax;
+        const int cap = g->seg ? n : qbits;
+        Buf<int> shist;
+        Buf<long long> shi;
+        if (g->seg) {
+            shist.alloc(ctx, (size_t)48 * g->nseg);
+            shi.alloc(ctx, (size_t)g->nseg);
+            hip_ok(hipMemsetAsync(shist.p, 0, shist.count * sizeof(int), s));
+        }
         // Each iteration is one fixed kernel sequence: count the inexact vertices
         // by (bound - c'), then either recompute the smallest bounds (up to 64 Q
         // sources, at least every one at or below c') or commit the round.  Every
@@ -818,9 +891,11 @@ struct ExactRun {
             for (int r = 0; r < per_sync; ++r) {
                 launch_round_reset(st.p, s);
                 launch_reduce(deg.p, nullptr, alive.p, n, st.p, s);
-                launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, s);
-                launch_decide(st.p, cap, s);
-                launch_pick(alive.p, deg.p, exact.p, n, st.p, srcl.p, cap, s);
+                launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, s, g->seg, shist.p);
+                launch_decide(st.p, qbits, s);
+                if (g->seg) launch_decide_seg(st.p, g->nseg, shist.p, shi.p, qbits, s);
+                launch_pick(alive.p, deg.p, exact.p, n, st.p, srcl.p, cap, s, g->seg, PL.gcnt.p, PL.sbit.p, qbits,
+                            g->seg ? shi.p : nullptr);
                 ms_batch(P, g->items, n, g->rp, g->col, alive.p, adeg.p, srcl.p, 0, &st.p->ms_ns, h, deg.p, st.p, s);
                 launch_mark_exact(srcl.p, st.p, exact.p, s);
                 launch_round_begin_gated(st.p, s);
@@ -1346,6 +1421,13 @@ void pack(kh_context* ctx, kh_graph* const* gs, int32_t count, Packed& P, bool s
         hip_ok(hipMemcpyAsync(P.lid.p, hl.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s));
         hip_ok(hipMemcpyAsync(P.Mv.p, hm.data(), 4 * (size_t)n, hipMemcpyHostToDevice, s));
     }
+    std::vector<int32_t> hseg((size_t)std::max(n, 1), 0);
+    for (int32_t i = 0; i < count; ++i)
+        std::fill(hseg.begin() + P.v_off[i], hseg.begin() + P.v_off[i + 1], i);
+    G.seg_own.alloc(ctx, hseg.size());
+    hip_ok(hipMemcpyAsync(G.seg_own.p, hseg.data(), 4 * hseg.size(), hipMemcpyHostToDevice, s));
+    G.seg = G.seg_own.p;
+    G.nseg = count;
     hip_ok(hipStreamSynchronize(s));  // the host tables above go out of scope
     G.rp = G.rp_own.p;
     G.col = G.col_own.p;
@@ -1526,7 +1608,7 @@ extern "C" kh_status kh_hdeg(kh_graph* g, int32_t h, const uint8_t* alive_in, ui
         srcl.alloc(ctx, n);
         deg.alloc(ctx, n);
         st.alloc(ctx, 1);
-        PL.alloc(ctx, n, pick_q(n));
+        PL.alloc(ctx, n, g->nnz, pick_q(n), g->items.nitems);
         PL.clear(s);
         init_state(st.p, s);
         launch_alive_from(alive_in, alive.p, n, s);

@@ -15,6 +15,10 @@ namespace kh {
 constexpr int kPullChunk = 128;
 // Arcs per chunk of the frontier-expansion kernels.
 constexpr int kExpandChunk = 256;
+// A BFS hop sweeps every work item once the previous frontier's adjacency
+// exceeds 1 / kSweepRatio of all arcs; below that it pulls only the alive
+// neighbours of the frontier.
+constexpr int kSweepRatio = 16;
 // Sampled lists store 32-bit keys ((255 - rank) << 24 | id): ascending key
 // order is rank descending, id ascending.  Needs n < 2^24.
 constexpr int32_t kMaxSampledN = (1 << 24) - 1;
@@ -135,10 +139,18 @@ void launch_lazy_candidates(const uint8_t* alive, const int64_t* deg, const uint
 void launch_set_flags(const int32_t* list, int count, uint8_t* flags, uint8_t v, hipStream_t s);
 // device-driven exact peel steps
 void launch_bound_hist(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
-                       hipStream_t s);
+                       hipStream_t s, const int32_t* seg = nullptr, int* shist = nullptr);
 void launch_decide(RoundState* st, int cap, hipStream_t s);
+// Picks the inexact alive vertices with deg <= st->hi as the next sources (at
+// most cap).  seg (nullable): segment (graph) of every vertex of a packed union;
+// then each source also gets a bit position sbit[slot] that is unique within its
+// segment, at most qbits per segment (gcnt: per-segment counters, all-zero
+// before; the scatter of the batch zeroes them again).
 void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
-                 int32_t* out, int cap, hipStream_t s);
+                 int32_t* out, int cap, hipStream_t s, const int32_t* seg = nullptr, int* gcnt = nullptr,
+                 int32_t* sbit = nullptr, int qbits = 0, const long long* shi = nullptr);
+// Per-segment thresholds shi[seg] (packed unions) from per-segment histograms.
+void launch_decide_seg(RoundState* st, int nseg, int* shist, long long* shi, int cap, hipStream_t s);
 void launch_mark_exact(const int32_t* list, RoundState* st, uint8_t* exact, hipStream_t s);
 void launch_round_begin_gated(RoundState* st, hipStream_t s);
 // R-mask BFS: after h hops rmask[v] holds bit (j mod 64) for every deleted r_j within
@@ -159,18 +171,51 @@ void launch_select_gated(const int64_t* key, uint8_t* alive, int32_t n, RoundSta
 
 // ---- kernels: bit-parallel multi-source bounded BFS (kh_msbfs.hip) ---------------------
 
+// Per-batch control block of the bit-parallel BFS (device memory, reset by the
+// batch's first kernel).  Lists are double-buffered by hop parity.
+struct MsCtl {
+    int fl_count[2];        // frontier list length (vertices with new bits at the hop)
+    long long fdeg[2];      // sum of the degrees of the frontier list
+    int cv_count[2];        // candidate vertices of the hop
+    int ci_count[2];        // candidate work items of the hop
+    int fc_count[2];        // 64-arc chunks of the frontier's vertices with more than 64 arcs
+    int tl_count;           // visited tiles (64 consecutive vertices holding a nonzero vis word)
+    int dense;              // 1 once a hop has swept the whole graph (sticky for the batch)
+    int dense_at;           // first dense hop (0: none)
+    int pad;
+};
+// All-zero between batches: the last kernel of a batch zeroes it.
+
 struct MsPlanes {
     int Q;                // 64-bit words per vertex (sources per batch = 64 Q)
     uint64_t* vis;        // n*Q, visited sets; kept all-zero between batches
     uint64_t* frA;        // n*Q, frontier (ping)
     uint64_t* frB;        // n*Q, frontier (pong)
     uint64_t* acc;        // n*Q, OR accumulator for split / pushed vertices; kept all-zero
-    uint32_t* bmA;        // ceil(n/32), bit per vertex: frontier word nonzero (ping)
+    uint32_t* bmA;        // ceil(n/32), bit per vertex: frontier word nonzero (ping); kept all-zero
     uint32_t* bmB;        // (pong)
-    uint32_t* bmT;        // touched-by-push bitmap
+    uint32_t* bmT;        // touched-by-push bitmap; kept all-zero
+    uint32_t* bmC;        // candidate bitmap; kept all-zero
     int32_t* touched;     // n, vertices touched by the push hop
     int* touched_count;   // device counter
-    uint32_t* cnt;        // 64 Q per-source counters
+    int32_t* flA;         // n, frontier list (hop parity 0)
+    int32_t* flB;         // n, frontier list (hop parity 1)
+    int2* fcA;            // n + nnz/64: (vertex, first arc) chunks of large frontier vertices (parity 0)
+    int2* fcB;            // (parity 1)
+    int32_t* tl;          // ceil(n/64), visited tile list
+    uint32_t* bmTile;     // bit per tile: listed in tl; kept all-zero
+    int32_t* cvA;         // n, candidate vertices (parity 0)
+    int32_t* cvB;         // n, (parity 1)
+    int32_t* ciA;         // nitems, candidate work items (parity 0)
+    int32_t* ciB;         // nitems, (parity 1)
+    MsCtl* ctl;
+    uint32_t* cnt;        // 64 Q per-source counters (per segment when seg != NULL); kept all-zero
+    // Segmented batches (a packed union of graphs): sources of different graphs
+    // never meet, so each graph uses the 64 Q bit positions on its own.
+    const int32_t* seg;   // nullable: segment of every vertex
+    const int32_t* sbit;  // nullable: bit position of source j (else j)
+    int* gcnt;            // per-segment pick counters (reset by the scatter)
+    int ns_cap;           // most sources of one batch (64 Q, or n when segmented)
     uint64_t* valid;      // Q words: bits of the batch's sources
     PullTimer* timer;     // nullable
 };
@@ -183,6 +228,8 @@ struct MsItems {
     uint8_t* split;   // 1 if the vertex has several items
     int32_t nsplit;
     int32_t* split_list;  // vertices with several items
+    int32_t* vitem;   // n: first item of each vertex (its items are consecutive)
+    int64_t nnz;      // arcs of the graph
 };
 
 // One batch of ns <= 64 Q sources: deg[src[j]] = |N(src[j]; h, X)| - 1.  With

@@ -148,3 +148,18 @@ def test_batch_rejects_early_stop(ctx):
     with pytest.raises(kh.KhError) as e:
         kh.core_batch([G], 2, epsilon=0.5, early_stop=True)
     assert e.value.code == -8
+
+
+def test_batch_many_tiny_graphs(ctx):
+    # hundreds of graphs of 1..12 vertices: one 64-vertex tile holds many graphs
+    rng = np.random.default_rng(5)
+    gs = [gg.random_small(int(rng.integers(1, 13)), float(rng.uniform(0.1, 0.7)), seed=i) for i in range(300)]
+    Gs = load(ctx, gs)
+    for h in (1, 2, 3):
+        say("batch tiny graphs", h)
+        cores, _ = kh.core_batch(Gs, h)
+        for g, c in zip(gs, cores):
+            assert np.array_equal(c.astype(np.int64), oracle.exact_core(g, h)), g.name
+        cs, _ = kh.core_batch(Gs, h, epsilon=0.5, seed=3, M_override=3)
+        for g, c in zip(gs, cs):
+            assert np.array_equal(c.astype(np.int64), oracle.sampled_core(g, h, oracle.ranks(g.n, 3), 3)), g.name
