@@ -153,6 +153,48 @@ kh_status kh_core(kh_graph *g, const kh_params *params, int32_t *core_out, kh_re
 kh_status kh_core_batch(kh_context *ctx, int32_t count, kh_graph *const *graphs, const kh_params *params,
                         int32_t *const *core_outs, kh_result *results, void *stream);
 
+/* ---- serving ------------------------------------------------------------------
+ * A request is one kh_core call (Sec. 2 ExactCore or Alg. 4 Core) queued on the
+ * context.  Worker threads, each with its own HIP stream, admit requests in
+ * arrival order as soon as a worker is free and the request's device-memory
+ * estimate fits next to the running ones; queued requests with identical
+ * kh_params join an admitted one in a single kh_core_batch call (continuous
+ * batching), so requests that arrive while others run overlap on the GPU.
+ * Each request's core_out and result equal those of kh_core on its graph
+ * alone.  The graph and core_out must stay valid until the request's result
+ * has been collected (kh_serve_poll / kh_serve_wait return other than
+ * KH_EBUSY); core_out is host memory unless params->flags has KH_OUT_DEVICE.
+ * For a served request, kh_result.seconds is the latency from submission to
+ * completion.  These calls are thread-safe; while a context serves, the
+ * context's profiling hooks see only work of the calling thread. */
+
+/* Start the serving loop of ctx: `workers` threads (0: 4), admission within
+ * hbm_budget_bytes (0: 80% of the device memory free now), at most queue_cap
+ * waiting requests (0: 65536), packed batches of at most batch_vertices
+ * vertices (0: 2^22).  KH_EBUSY if ctx already serves.  kh_serve_submit starts
+ * the loop with the defaults when needed. */
+kh_status kh_serve_start(kh_context *ctx, int32_t workers, uint64_t hbm_budget_bytes, int32_t queue_cap,
+                         int64_t batch_vertices);
+
+/* Queue kh_core(g, params, core_out) and return its ticket.  KH_EINVAL for
+ * invalid params (as kh_core) or a graph of another context; KH_EBUSY when the
+ * queue is full or the loop is stopping. */
+kh_status kh_serve_submit(kh_context *ctx, kh_graph *g, const kh_params *params, int32_t *core_out,
+                          uint64_t *ticket);
+
+/* Result of a ticket: KH_EBUSY while the request waits or runs; otherwise the
+ * request's own status (KH_OK, or the error kh_core returned), with *res
+ * filled (res nullable), and the ticket is retired.  KH_ENOTFOUND for unknown
+ * or retired tickets. */
+kh_status kh_serve_poll(kh_context *ctx, uint64_t ticket, kh_result *res);
+
+/* As kh_serve_poll, but blocks until the request has finished. */
+kh_status kh_serve_wait(kh_context *ctx, uint64_t ticket, kh_result *res);
+
+/* Finish every queued request, stop the workers and drop uncollected results.
+ * No call may wait on this context meanwhile.  kh_context_destroy does this too. */
+kh_status kh_serve_stop(kh_context *ctx);
+
 /* h-degrees deg_h(v;X) = |N(v;h,X)| - 1 (Sec. 2) of every vertex of X, where
  * X is given by alive[n] (uint8, nonzero = in X; device; NULL = all of V).
  * deg_out[n] (int32; host unless KH_OUT_DEVICE) gets -1 for v outside X.

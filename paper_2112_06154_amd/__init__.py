@@ -5,5 +5,5 @@ level of Tatti, "Fast computation of distance-generalized cores using
 sampling" (arXiv 2112.06154), computed by hand-written HIP kernels behind the
 C ABI in include/khcore.h.  This package is only the Python binding.
 """
-from .khcore import (Context, Graph, KhError, buffer_size, core, core_batch, dense, hdeg, ranks,  # noqa: F401
-                     sampled_lists, status_str, validate_csr)
+from .khcore import (Context, Graph, KhError, Server, buffer_size, core, core_batch, dense, hdeg,  # noqa: F401
+                     ranks, sampled_lists, status_str, validate_csr)

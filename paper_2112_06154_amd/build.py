@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libkhcore.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["kh_graph.hip", "kh_msbfs.hip", "kh_union.hip", "kh_host.cpp"]
+SOURCES = ["kh_graph.hip", "kh_msbfs.hip", "kh_union.hip", "kh_host.cpp", "kh_serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -18,7 +18,7 @@ FLAGS = [
     # packed fp32 instructions stay off (this library does integer work only)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-    "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function", "-pthread",
 ]
 
 
@@ -34,7 +34,7 @@ def build(verbose: bool = False) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
-    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs)
     os.replace(tmp, OUT)
     if verbose:
         print("built", OUT)

@@ -687,16 +687,31 @@ __global__ void k_bound_hist(const uint8_t* __restrict__ alive, const int64_t* _
                              const uint8_t* __restrict__ exact, int32_t n, RoundState* st,
                              const int32_t* __restrict__ seg, int* __restrict__ shist) {
     __shared__ int h[48];
+    __shared__ int hs[48];  // segment histogram of the block's first vertex of the step
     if (threadIdx.x < 48) h[threadIdx.x] = 0;
     __syncthreads();
     if (st->alive_count > 0) {
         const long long c = cur_level(st);
-        for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-            if (alive[v] && !exact[v]) {
+        for (int32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+            const int32_t v = base + threadIdx.x;
+            int b = -1;
+            if (v < n && alive[v] && !exact[v]) {
                 const long long d = deg[v] - c;
-                const int b = d <= 0 ? 0 : min(47, 64 - __clzll((unsigned long long)d));
+                b = d <= 0 ? 0 : min(47, 64 - __clzll((unsigned long long)d));
                 atomicAdd(&h[b], 1);
-                if (shist) atomicAdd(&shist[(size_t)seg[v] * 48 + b], 1);
+            }
+            if (shist) {
+                // the block's vertices mostly share one segment: count those in LDS
+                if (threadIdx.x < 48) hs[threadIdx.x] = 0;
+                __syncthreads();
+                const int32_t g0 = seg[base];
+                if (b >= 0) {
+                    const int32_t g = seg[v];
+                    if (g == g0) atomicAdd(&hs[b], 1);
+                    else atomicAdd(&shist[(size_t)g * 48 + b], 1);
+                }
+                __syncthreads();
+                if (threadIdx.x < 48 && hs[threadIdx.x]) atomicAdd(&shist[(size_t)g0 * 48 + threadIdx.x], hs[threadIdx.x]);
             }
         }
     }

@@ -18,7 +18,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <mutex>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -60,7 +62,7 @@ void hip_ok(hipError_t e) {
 struct kh_context {
     int device = 0;
     uint64_t budget = 0;
-    uint64_t used = 0;
+    std::atomic<uint64_t> used{0};
     size_t lds_per_block = 65536;
     int num_cu = 0;
     RoundState* host_state = nullptr;  // pinned mirror of the device round state
@@ -73,6 +75,15 @@ struct kh_context {
 };
 
 namespace {
+
+// Threads of the serving loop run requests concurrently on one context: each
+// has its own pinned mirror of the device round state, and profiling (whose
+// event slots the context shares) stays with the owner thread.
+thread_local RoundState* tl_state = nullptr;
+thread_local bool tl_worker = false;
+
+RoundState* hstate(kh_context* ctx) { return tl_state ? tl_state : ctx->host_state; }
+bool prof_active(const kh_context* ctx) { return ctx->prof_on && !tl_worker; }
 
 template <typename T>
 struct Buf {
@@ -102,12 +113,17 @@ struct Buf {
         release();
         ctx = c;
         const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
-        if (ctx->budget && ctx->used + bytes > ctx->budget) fail(KH_ENOMEM);
+        const uint64_t before = ctx->used.fetch_add(bytes);
+        if (ctx->budget && before + bytes > ctx->budget) {
+            ctx->used.fetch_sub(bytes);
+            fail(KH_ENOMEM);
+        }
         void* q = nullptr;
-        hip_ok(hipMalloc(&q, bytes));
+        const hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) ctx->used.fetch_sub(bytes);
+        hip_ok(e);
         p = static_cast<T*>(q);
         count = n;
-        ctx->used += bytes;
     }
     void release() {
         if (p) {
@@ -135,7 +151,9 @@ struct kh_graph {
     const int32_t* rp = nullptr;
     const int32_t* col = nullptr;
     std::vector<int32_t> h_rp;
-    // work items of the h-degree pull kernel (built on first use)
+    // work items of the h-degree pull kernel (built on first use, under the lock:
+    // served requests on one graph may run on several threads)
+    std::mutex items_lock;
     bool items_built = false;
     Buf<int32_t> it_u, it_beg, it_end, split_list, vitem;
     // packed unions of several graphs: segment (graph) of every vertex
@@ -228,8 +246,21 @@ extern "C" kh_status kh_context_create(int32_t device, uint64_t hbm_budget_bytes
     return KH_OK;
 }
 
+namespace kh {
+void worker_thread_begin(RoundState* pinned) {
+    tl_state = pinned;
+    tl_worker = true;
+}
+void worker_thread_end() {
+    tl_state = nullptr;
+    tl_worker = false;
+}
+kh_context* graph_context(const kh_graph* g);
+}  // namespace kh
+
 extern "C" void kh_context_destroy(kh_context* ctx) {
     if (!ctx) return;
+    kh::serve_shutdown(ctx);
     if (ctx->host_state) (void)hipHostFree(ctx->host_state);
     for (auto& T : ctx->timer) {
         if (T.ev) {
@@ -258,7 +289,7 @@ void prof_collect(kh_context* ctx) {
 }
 
 void prof_add_counters(kh_context* ctx, const RoundState& hs) {
-    if (!ctx->prof_on) return;
+    if (!prof_active(ctx)) return;
     prof_collect(ctx);
     ctx->prof_bytes[0] += hs.pull_bytes;
     ctx->prof_gather += hs.pull_gather;
@@ -411,6 +442,8 @@ extern "C" kh_status kh_graph_load_csr(kh_context* ctx, int32_t n, int64_t nnz, 
 }
 
 extern "C" void kh_graph_free(kh_graph* g) { delete g; }
+kh_context* kh::graph_context(const kh_graph* g) { return g ? g->ctx : nullptr; }
+int kh::context_device(const kh_context* ctx) { return ctx->device; }
 extern "C" int32_t kh_graph_n(const kh_graph* g) { return g ? g->n : -1; }
 extern "C" int64_t kh_graph_nnz(const kh_graph* g) { return g ? g->nnz : -1; }
 
@@ -441,6 +474,7 @@ void check_params(const kh_graph* g, const kh_params* P) {
 // kPullChunk arcs; split pieces first, then whole vertices by decreasing degree,
 // so that the groups of a wave see items of similar length.
 void build_items(kh_graph* g, hipStream_t s) {
+    std::lock_guard<std::mutex> lock(g->items_lock);
     if (g->items_built) return;
     const int32_t n = g->n;
     const std::vector<int32_t>& rp = g->h_rp;
@@ -625,7 +659,7 @@ void hdeg_sources(kh_graph* g, Planes& PL, const uint8_t* alive, const int32_t* 
                   int h, int64_t* deg, RoundState* st, hipStream_t s) {
     int64_t done = 0;
     kh_context* ctx = g->ctx;
-    PL.timer = ctx->prof_on ? &ctx->timer[0] : nullptr;
+    PL.timer = prof_active(ctx) ? &ctx->timer[0] : nullptr;
     while (done < count) {
         if (PL.timer && PL.timer->used + 8 >= PL.timer->cap) prof_collect(ctx);
         const int64_t rest = count - done;
@@ -643,7 +677,7 @@ void hdeg_sources(kh_graph* g, Planes& PL, const uint8_t* alive, const int32_t* 
 
 void read_state(kh_context* ctx, RoundState* dst_dev, hipStream_t s) {
     hip_ok(hipGetLastError());
-    hip_ok(hipMemcpyAsync(ctx->host_state, dst_dev, sizeof(RoundState), hipMemcpyDeviceToHost, s));
+    hip_ok(hipMemcpyAsync(hstate(ctx), dst_dev, sizeof(RoundState), hipMemcpyDeviceToHost, s));
     hip_ok(hipStreamSynchronize(s));
 }
 
@@ -909,15 +943,15 @@ struct ExactRun {
             }
             s = keep;
         };
-        const bool use_graph = !graphs_off() && !ctx->prof_on;
-        PL.timer = ctx->prof_on ? &ctx->timer[0] : nullptr;
+        const bool use_graph = !graphs_off() && !prof_active(ctx);
+        PL.timer = prof_active(ctx) ? &ctx->timer[0] : nullptr;
         const hipStream_t q = rp.prepare(caller, use_graph, record);
         for (;;) {
             rp.run(record);
-            if (ctx->prof_on) prof_collect(ctx);
+            if (prof_active(ctx)) prof_collect(ctx);
             iters += per_sync;
             read_state(ctx, st.p, q);
-            const RoundState hs = *ctx->host_state;
+            const RoundState hs = *hstate(ctx);
             if (hs.mode == 2) break;
             if (iters > 4ll * n + 4096) fail(KH_EDEVICE);
             if (hs.fepoch > (1 << 30)) {
@@ -928,7 +962,7 @@ struct ExactRun {
             trace_round(hs, "lazy", t0);
         }
         hip_ok(hipStreamSynchronize(q));
-        fin = *ctx->host_state;
+        fin = *hstate(ctx);
         prof_add_counters(ctx, fin);
     }
 
@@ -948,7 +982,7 @@ struct ExactRun {
         launch_round_reset(st.p, s);
         launch_compact_alive(alive.p, n, srcl.p, &st.p->aff_fill, s);
         read_state(ctx, st.p, s);
-        hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, ctx->host_state->aff_fill, h, deg.p, st.p, s);
+        hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, hstate(ctx)->aff_fill, h, deg.p, st.p, s);
         int32_t epoch = 0;
         for (;;) {
             ++epoch;
@@ -957,13 +991,13 @@ struct ExactRun {
             launch_round_begin(st.p, ck.p, cs.p, cr.p, 0, s);
             delete_round(epoch, key);
             read_state(ctx, st.p, s);
-            const RoundState hs = *ctx->host_state;
+            const RoundState hs = *hstate(ctx);
             if (hs.alive_count == 0) break;
             if (hs.rounds > n + 1) fail(KH_EDEVICE);
             trace_round(hs, "replay", t0);
             if (hs.aff_fill > 0) hdeg_sources(g, PL, alive.p, adeg.p, alist.p, hs.aff_fill, h, deg.p, st.p, s);
         }
-        fin = *ctx->host_state;
+        fin = *hstate(ctx);
         prof_add_counters(ctx, fin);
         cands = read_candidates(fin, ck, cs, cr, s);
     }
@@ -1127,7 +1161,7 @@ struct SampledRun {
         int32_t* changed[2] = {chA.p, chB.p};
         const int batch = 8;
         const auto t_start = Clock::now();
-        PullTimer* utimer = ctx->prof_on ? &ctx->timer[1] : nullptr;
+        PullTimer* utimer = prof_active(ctx) ? &ctx->timer[1] : nullptr;
         const hipStream_t caller = s;
         Replay rp;
         auto record = [&](hipStream_t q) {
@@ -1157,22 +1191,22 @@ struct SampledRun {
                                 L.kk[h].p, M, Mv, d.p, st.p, q);
             }
         };
-        const hipStream_t q = rp.prepare(caller, !graphs_off() && !ctx->prof_on, record);
+        const hipStream_t q = rp.prepare(caller, !graphs_off() && !prof_active(ctx), record);
         for (;;) {
             rp.run(record);
-            if (ctx->prof_on) prof_collect(ctx);
+            if (prof_active(ctx)) prof_collect(ctx);
             read_state(ctx, st.p, q);
-            if (ctx->host_state->alive_count == 0) break;
+            if (hstate(ctx)->alive_count == 0) break;
             // every round deletes at least the minimum vertex
-            if (ctx->host_state->rounds > n + 1) fail(KH_EDEVICE);
-            if (trace_on() && ((ctx->host_state->rounds & 255) < batch))
+            if (hstate(ctx)->rounds > n + 1) fail(KH_EDEVICE);
+            if (trace_on() && ((hstate(ctx)->rounds & 255) < batch))
                 std::fprintf(stderr, "[kh sampled] round %d c %lld alive %d removed %d worklist %d merged %d t %.3fs\n",
-                             ctx->host_state->rounds, ctx->host_state->c, ctx->host_state->alive_count,
-                             ctx->host_state->rcount, ctx->host_state->wl_count, ctx->host_state->rc_count,
+                             hstate(ctx)->rounds, hstate(ctx)->c, hstate(ctx)->alive_count,
+                             hstate(ctx)->rcount, hstate(ctx)->wl_count, hstate(ctx)->rc_count,
                              std::chrono::duration<double>(Clock::now() - t_start).count());
         }
         hip_ok(hipStreamSynchronize(q));
-        fin = *ctx->host_state;
+        fin = *hstate(ctx);
         prof_add_counters(ctx, fin);
         cands = read_candidates(fin, ck, cs, cr, s);
     }
@@ -1617,11 +1651,11 @@ extern "C" kh_status kh_hdeg(kh_graph* g, int32_t h, const uint8_t* alive_in, ui
         launch_round_reset(st.p, s);
         launch_compact_alive(alive.p, n, srcl.p, &st.p->aff_fill, s);
         read_state(ctx, st.p, s);
-        hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, ctx->host_state->aff_fill, he, deg.p, st.p, s);
+        hdeg_sources(g, PL, alive.p, adeg.p, srcl.p, hstate(ctx)->aff_fill, he, deg.p, st.p, s);
         finish_core(ctx, deg.p, n, deg_out, (flags & KH_OUT_DEVICE) != 0, s, nullptr);
         read_state(ctx, st.p, s);
-        if (edges_traversed) *edges_traversed = (int64_t)ctx->host_state->te;
-        prof_add_counters(ctx, *ctx->host_state);
+        if (edges_traversed) *edges_traversed = (int64_t)hstate(ctx)->te;
+        prof_add_counters(ctx, *hstate(ctx));
     } catch (const KhError& e) {
         return e.code;
     } catch (const std::bad_alloc&) {

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "../../include/khcore.h"
+
 namespace kh {
 
 // ---- sizes --------------------------------------------------------------------
@@ -280,5 +282,15 @@ void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int3
 void launch_estimate(const int32_t* worklist, const int* wl_count, int32_t n, const uint8_t* alive,
                      const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, const int32_t* Mv,
                      int64_t* d, RoundState* st, hipStream_t s);
+
+// ---- serving (kh_serve.cpp) and its hooks into the engines (kh_host.cpp) -------------
+// A serving thread runs requests with its own pinned round-state mirror, and
+// without the context's profiling slots.
+void worker_thread_begin(RoundState* pinned);
+void worker_thread_end();
+// Stops the context's serving loop, if any (kh_context_destroy calls it).
+void serve_shutdown(kh_context* ctx);
+kh_context* graph_context(const kh_graph* g);
+int context_device(const kh_context* ctx);
 
 }  // namespace kh

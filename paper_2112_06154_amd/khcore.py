@@ -38,7 +38,7 @@ KH_OUT_DEVICE = 8
 EXPORTED = [
     "kh_status_str", "kh_buffer_size", "kh_validate_csr", "kh_context_create", "kh_context_destroy",
     "kh_graph_load_csr", "kh_graph_free", "kh_graph_n", "kh_graph_nnz", "kh_core", "kh_core_batch", "kh_hdeg",
-    "kh_ranks",
+    "kh_ranks", "kh_serve_start", "kh_serve_submit", "kh_serve_poll", "kh_serve_wait", "kh_serve_stop",
     "kh_sampled_lists", "kh_dense", "kh_profile_enable", "kh_profile_read",
 ]
 
@@ -99,6 +99,16 @@ def lib():
         L.kh_core.restype = i32
         L.kh_core_batch.argtypes = [P, i32, P, ctypes.POINTER(Params), P, P, P]
         L.kh_core_batch.restype = i32
+        L.kh_serve_start.argtypes = [P, i32, u64, i32, i64]
+        L.kh_serve_start.restype = i32
+        L.kh_serve_submit.argtypes = [P, P, ctypes.POINTER(Params), P, ctypes.POINTER(u64)]
+        L.kh_serve_submit.restype = i32
+        L.kh_serve_poll.argtypes = [P, u64, ctypes.POINTER(Result)]
+        L.kh_serve_poll.restype = i32
+        L.kh_serve_wait.argtypes = [P, u64, ctypes.POINTER(Result)]
+        L.kh_serve_wait.restype = i32
+        L.kh_serve_stop.argtypes = [P]
+        L.kh_serve_stop.restype = i32
         L.kh_hdeg.argtypes = [P, i32, P, u32, P, ctypes.POINTER(i64), P]
         L.kh_hdeg.restype = i32
         L.kh_ranks.argtypes = [P, i32, u64, u32, P, P]
@@ -284,6 +294,50 @@ def core_batch(graphs, h: int, epsilon: float = 0.0, outs=None, stream=None, **k
            "kh_core_batch")
     cores = [o[:g.n] if isinstance(o, np.ndarray) else o for o, g in zip(outs, graphs)]
     return cores, [res[i].as_dict() for i in range(count)]
+
+
+class Server:
+    """The context's serving loop (kh_serve_*): submit returns a ticket, poll
+    returns None while the request is pending and (core, result) once done.
+    Output arrays are kept alive here until collected."""
+
+    def __init__(self, ctx: Context, workers: int = 0, hbm_budget: int = 0, queue_cap: int = 0,
+                 batch_vertices: int = 0):
+        self.ctx = ctx
+        _check(lib().kh_serve_start(ctx.handle, workers, hbm_budget, queue_cap, batch_vertices), "kh_serve_start")
+        self._pending = {}
+
+    def submit(self, graph: Graph, h: int, epsilon: float = 0.0, out=None, **kw) -> int:
+        p = make_params(h, epsilon, out_device=out is not None, **kw)
+        if out is None:
+            out = np.zeros(max(graph.n, 1), np.int32)
+        t = ctypes.c_uint64()
+        _check(lib().kh_serve_submit(self.ctx.handle, graph.handle, ctypes.byref(p), _ptr(out), ctypes.byref(t)),
+               "kh_serve_submit")
+        self._pending[t.value] = (out, graph)
+        return t.value
+
+    def _collect(self, ticket: int, wait: bool):
+        res = Result()
+        fn = lib().kh_serve_wait if wait else lib().kh_serve_poll
+        code = fn(self.ctx.handle, ticket, ctypes.byref(res))
+        if code == KH_EBUSY:
+            return None
+        out, graph = self._pending.pop(ticket, (None, None))
+        _check(code, "kh_serve_wait" if wait else "kh_serve_poll")
+        if isinstance(out, np.ndarray):
+            out = out[:graph.n]
+        return out, res.as_dict()
+
+    def poll(self, ticket: int):
+        return self._collect(ticket, False)
+
+    def wait(self, ticket: int):
+        return self._collect(ticket, True)
+
+    def stop(self):
+        _check(lib().kh_serve_stop(self.ctx.handle), "kh_serve_stop")
+        self._pending.clear()
 
 
 def hdeg(graph: Graph, h: int, alive=None, out=None, stream=None):

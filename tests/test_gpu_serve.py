@@ -1,0 +1,138 @@
+"""GPU tests of the serving loop (kh_serve_*): every request's result is the
+same alone and in a mix of concurrent requests, and the ticket protocol and
+admission behave as declared."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+
+torch = pytest.importorskip("torch")
+kh = pytest.importorskip("paper_2112_06154_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = kh.Context(0)
+    yield c
+    c.close()
+
+
+def pool(count=10, seed=3):
+    """Chung-Lu graphs (gamma 2.2, average degree 10) of uneven size."""
+    sizes = gg.lognormal_sizes(count, 800, 1.0, 60, 6000, seed)
+    return [gg.chung_lu(int(n), 5 * int(n), 2.2, seed=seed + i) for i, n in enumerate(sizes)]
+
+
+def requests(gs, count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        gi = int(rng.integers(len(gs)))
+        h = int(rng.integers(2, 4))
+        eps = 0.5 if rng.random() < 0.5 else 0.0
+        out.append((gi, h, eps))
+    return out
+
+
+def kwargs(eps):
+    return dict(seed=9) if eps > 0 else {}
+
+
+def test_serve_alone_equals_mix(ctx):
+    gs = pool()
+    Gs = [kh.Graph.from_gg(ctx, g) for g in gs]
+    reqs = requests(gs, 48, 1)
+    alone = {}
+    for gi, h, eps in set(reqs):
+        say("alone", gi, h, eps)
+        alone[(gi, h, eps)] = kh.core(Gs[gi], h, epsilon=eps, **kwargs(eps))[0]
+    srv = kh.Server(ctx, workers=4)
+    try:
+        say("mix", len(reqs))
+        tickets = [srv.submit(Gs[gi], h, epsilon=eps, **kwargs(eps)) for gi, h, eps in reqs]
+        for t, key in zip(tickets, reqs):
+            core, res = srv.wait(t)
+            assert np.array_equal(core, alone[key]), key
+            assert res["max_core"] == int(alone[key].max())
+            assert res["seconds"] > 0
+        # and against the oracle for the smallest graphs
+        small = sorted(range(len(gs)), key=lambda i: gs[i].n)[:3]
+        for gi in small:
+            for h in (2, 3):
+                t1 = srv.submit(Gs[gi], h)
+                t2 = srv.submit(Gs[gi], h, epsilon=0.5, seed=9)
+                assert np.array_equal(srv.wait(t1)[0].astype(np.int64), oracle.exact_core(gs[gi], h))
+                M = oracle.M_int(gs[gi].n, 0.5)
+                want = oracle.sampled_core(gs[gi], h, oracle.ranks(gs[gi].n, 9), M)
+                assert np.array_equal(srv.wait(t2)[0].astype(np.int64), want)
+    finally:
+        srv.stop()
+
+
+def test_serve_ticket_protocol(ctx):
+    g = gg.erdos_renyi(300, 900, seed=2)
+    G = kh.Graph.from_gg(ctx, g)
+    srv = kh.Server(ctx, workers=2)
+    try:
+        with pytest.raises(kh.KhError) as e:
+            srv.poll(123456789)
+        assert e.value.code == kh.khcore.KH_ENOTFOUND
+        t = srv.submit(G, 2)
+        got = None
+        while got is None:
+            got = srv.poll(t)
+        assert np.array_equal(got[0].astype(np.int64), oracle.exact_core(g, 2))
+        with pytest.raises(kh.KhError) as e:
+            srv.poll(t)  # retired
+        assert e.value.code == kh.khcore.KH_ENOTFOUND
+        with pytest.raises(kh.KhError) as e:
+            srv.submit(G, 0)
+        assert e.value.code == -1
+        # a second start on a serving context is refused
+        with pytest.raises(kh.KhError) as e:
+            kh.Server(ctx)
+        assert e.value.code == kh.khcore.KH_EBUSY
+    finally:
+        srv.stop()
+
+
+def test_serve_tiny_budget_runs_one_at_a_time(ctx):
+    gs = pool(6, seed=11)
+    Gs = [kh.Graph.from_gg(ctx, g) for g in gs]
+    srv = kh.Server(ctx, workers=3, hbm_budget=1, batch_vertices=1)
+    try:
+        say("tiny budget")
+        ts = [srv.submit(G, 2) for G in Gs] + [srv.submit(G, 3, epsilon=0.5, seed=4) for G in Gs]
+        for i, t in enumerate(ts):
+            core, _ = srv.wait(t)
+            G = Gs[i % len(Gs)]
+            want = kh.core(G, 2)[0] if i < len(Gs) else kh.core(G, 3, epsilon=0.5, seed=4)[0]
+            assert np.array_equal(core, want)
+    finally:
+        srv.stop()
+
+
+def test_serve_device_outputs(ctx):
+    gs = pool(5, seed=21)
+    Gs = [kh.Graph.from_gg(ctx, g) for g in gs]
+    srv = kh.Server(ctx)
+    try:
+        outs = [torch.full((g.n,), -1, dtype=torch.int32, device="cuda:0") for g in gs]
+        ts = [srv.submit(G, 2, out=o) for G, o in zip(Gs, outs)]
+        for t, G, o in zip(ts, Gs, outs):
+            srv.wait(t)
+            assert np.array_equal(o.cpu().numpy(), kh.core(G, 2)[0])
+    finally:
+        srv.stop()
