@@ -94,6 +94,154 @@ def cpu_baseline(g, hs, budget_s: float):
                       f"about {budget_s:.0f} s per h, single thread", "per_h": per_h}
 
 
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def bench_batch(kh, ctx, args):
+    """Batch workload: many graphs of uneven size (n log-uniform on [100, 50000],
+    half Erdos-Renyi with average degree 6, half Barabasi-Albert with 3 edges
+    per new vertex), exact (k,h)-cores of all of them by kh_core_batch, against
+    kh_core looped over a seeded sample of them (extrapolated)."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    t0 = time.time()
+    gs = gg.batch_workload(count=args.batch_count)
+    log(f"batch workload: {len(gs)} graphs, {sum(g.n for g in gs)} vertices, generated in {time.time() - t0:.1f}s")
+    Gs = [kh.Graph.from_gg(ctx, g) for g in gs]
+    torch.cuda.synchronize()
+    out = {"graphs": len(gs), "vertices": int(sum(g.n for g in gs)), "edges": int(sum(g.col.size for g in gs) // 2)}
+    rng = np.random.default_rng(7)
+    half = len(gs) // 2
+    sample = sorted(rng.choice(half, args.batch_loop_sample // 2, replace=False).tolist() +
+                    (half + rng.choice(len(gs) - half, args.batch_loop_sample // 2, replace=False)).tolist())
+    for h in [int(x) for x in args.batch_hs.split(",")]:
+        te = 0
+        for G in Gs:
+            te += kh.hdeg(G, h)[1]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        cores, res = kh.core_batch(Gs, h)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t
+        log(f"batch h={h}: {tb:.2f}s")
+        t = time.perf_counter()
+        same = True
+        te_s = 0
+        for i in sample:
+            c, _ = kh.core(Gs[i], h)
+            same &= bool(np.array_equal(c, cores[i]))
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t
+        for i in sample:
+            te_s += kh.hdeg(Gs[i], h)[1]
+        loop_est = tl * te / max(te_s, 1)
+        out[f"h{h}"] = {"seconds": round(tb, 3), "graphs_per_s": round(len(gs) / tb, 2),
+                        "edges_traversed_per_s": te / tb, "edges_traversed": te,
+                        "rounds": res[0]["rounds"],
+                        "loop_sample": {"graphs": len(sample), "seconds": round(tl, 3),
+                                        "edges_traversed": te_s, "identical_to_batch": same},
+                        "loop_estimate_s": round(loop_est, 2), "speedup_vs_loop": round(loop_est / tb, 2)}
+    return out
+
+
+def bench_serve(kh, ctx, args):
+    """Serving workload: a pool of Chung-Lu graphs (gamma 2.2, average degree
+    10, n lognormal with median 20000 and sigma 1.0 clipped to [1000, cap], one
+    graph of exactly cap vertices); Poisson arrivals at --serve-qps for
+    --serve-seconds, each request a uniform graph, h uniform in {2, 3} and mode
+    uniform in {exact, eps = 0.5}.  Latency = arrival to result ready.  Requests
+    still queued --serve-grace seconds after the last arrival are withdrawn and
+    reported as unserved (latency percentiles cover the completed ones)."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    t0 = time.time()
+    cap = args.serve_max_n
+    sizes = gg.lognormal_sizes(args.serve_pool, 20_000, 1.0, 1_000, cap, 5)
+    sizes[0] = cap
+    gs = [gg.chung_lu(int(n), 5 * int(n), 2.2, seed=100 + i) for i, n in enumerate(sizes)]
+    Gs = [kh.Graph.from_gg(ctx, g) for g in gs]
+    torch.cuda.synchronize()
+    log(f"serve pool: {len(gs)} graphs, {int(sizes.sum())} vertices, built in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(11)
+    nreq = int(args.serve_qps * args.serve_seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.serve_qps, nreq))
+    picks = rng.integers(len(gs), size=nreq)
+    hs = rng.integers(2, 4, size=nreq)
+    modes = rng.random(nreq) < 0.5
+    srv = kh.Server(ctx, workers=args.serve_workers)
+    t_start = time.perf_counter()
+    done = {}
+    pending = []
+    i = 0
+    last_log = 0.0
+    cancelled = 0
+    deadline = args.serve_seconds + args.serve_grace
+    while i < nreq or pending:
+        now = time.perf_counter() - t_start
+        while i < nreq and arrivals[i] <= now:
+            eps = 0.5 if modes[i] else 0.0
+            kw = dict(seed=1) if eps > 0 else {}
+            tk = srv.submit(Gs[picks[i]], int(hs[i]), epsilon=eps, **kw)
+            pending.append((tk, i))
+            i += 1
+        still = []
+        for tk, j in pending:
+            r = srv.poll(tk)
+            if r is None:
+                still.append((tk, j))
+            else:
+                done[j] = time.perf_counter() - t_start - arrivals[j]
+        pending = still
+        if now - last_log >= 5.0:
+            log(f"serve t={now:.0f}s submitted {i} done {len(done)} pending {len(pending)}")
+            last_log = now
+        if now > deadline and i >= nreq:
+            # withdraw what still waits in the queue; let the running ones finish
+            rest = []
+            for tk, j in pending:
+                if srv.cancel(tk):
+                    cancelled += 1
+                else:
+                    rest.append((tk, j))
+            while rest:
+                still = []
+                for tk, j in rest:
+                    if srv.poll(tk) is None:
+                        still.append((tk, j))
+                    else:
+                        done[j] = time.perf_counter() - t_start - arrivals[j]
+                rest = still
+                now = time.perf_counter() - t_start
+                if now - last_log >= 5.0:
+                    log(f"serve t={now:.0f}s: waiting for {len(rest)} running requests, done {len(done)}")
+                    last_log = now
+                time.sleep(0.002)
+            pending = []
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t_start
+    srv.stop()
+    fin = sorted(done)
+    lat = np.array([done[j] for j in fin])
+    cls = {}
+    for j in fin:
+        key = f"{'sampled' if modes[j] else 'exact'}_h{int(hs[j])}"
+        cls.setdefault(key, []).append(lat[j])
+    return {"requests": nreq, "completed": len(fin), "withdrawn_unserved": cancelled,
+            "qps_offered": args.serve_qps, "seconds_offered": args.serve_seconds,
+            "wall_s": round(wall, 3), "qps_served": round(len(fin) / wall, 2),
+            "p50_ms": round(1e3 * percentile(lat, 50), 3), "p99_ms": round(1e3 * percentile(lat, 99), 3),
+            "max_ms": round(1e3 * float(lat.max()), 3), "workers": args.serve_workers,
+            "pool": {"graphs": len(gs), "max_n": int(cap), "median_n": int(np.median(sizes))},
+            "per_class": {k: {"n": len(v), "p50_ms": round(1e3 * percentile(v, 50), 3),
+                              "p99_ms": round(1e3 * percentile(v, 99), 3)} for k, v in sorted(cls.items())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +252,19 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=8.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--batch", action="store_true", help="also measure the batch workload (kh_core_batch)")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-hs", default="2,3")
+    ap.add_argument("--batch-loop-sample", type=int, default=32)
+    ap.add_argument("--serve", action="store_true", help="also measure the serving workload (kh_serve_*)")
+    ap.add_argument("--serve-qps", type=float, default=200.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-pool", type=int, default=256)
+    ap.add_argument("--serve-max-n", type=int, default=2_000_000)
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-grace", type=float, default=60.0,
+                    help="seconds after the last arrival before queued requests are withdrawn")
+    ap.add_argument("--skip-main", action="store_true", help="only the --batch / --serve measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -116,6 +277,16 @@ def main():
 
     stages = [s for s in args.stages.split(",") if s]
     hs = [int(x) for x in args.hs.split(",")]
+    if args.skip_main:
+        torch.cuda.set_device(0)
+        ctx = kh.Context(0)
+        extra = {}
+        if args.batch:
+            extra["batch"] = bench_batch(kh, ctx, args)
+        if args.serve:
+            extra["serve"] = bench_serve(kh, ctx, args)
+        print(json.dumps(extra))
+        return
     t0 = time.time()
     g = gg.workload("cl1m")
     log(f"graph {WORKLOAD}: generated in {time.time() - t0:.1f}s")
@@ -216,6 +387,10 @@ def main():
         "te_per_decomposition": {str(h): te_pass[h] for h in hs},
         "stages_detail": rec,
     }
+    if args.batch:
+        line["batch"] = bench_batch(kh, ctx, args)
+    if args.serve:
+        line["serve"] = bench_serve(kh, ctx, args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, hs, args.cpu_budget)
     print(json.dumps(line))

@@ -20,7 +20,9 @@
  *   - All device arithmetic is integer.  The only floating point is the
  *     buffer size M (computed once on the host in binary64) and the reported
  *     density.
- *   - A context is used by one host thread at a time.
+ *   - Calls on one context may come from several host threads at once
+ *     (each call keeps its own device state); profiling (kh_profile_*)
+ *     records only calls made while no other thread uses the context.
  */
 #ifndef KHCORE_H
 #define KHCORE_H
@@ -171,8 +173,9 @@ kh_status kh_core_batch(kh_context *ctx, int32_t count, kh_graph *const *graphs,
 /* Start the serving loop of ctx: `workers` threads (0: 4), admission within
  * hbm_budget_bytes (0: 80% of the device memory free now), at most queue_cap
  * waiting requests (0: 65536), packed batches of at most batch_vertices
- * vertices (0: 2^22).  KH_EBUSY if ctx already serves.  kh_serve_submit starts
- * the loop with the defaults when needed. */
+ * vertices (0: 2^20; a packed batch finishes all its requests together).
+ * KH_EBUSY if ctx already serves.  kh_serve_submit starts the loop with the
+ * defaults when needed. */
 kh_status kh_serve_start(kh_context *ctx, int32_t workers, uint64_t hbm_budget_bytes, int32_t queue_cap,
                          int64_t batch_vertices);
 
@@ -190,6 +193,11 @@ kh_status kh_serve_poll(kh_context *ctx, uint64_t ticket, kh_result *res);
 
 /* As kh_serve_poll, but blocks until the request has finished. */
 kh_status kh_serve_wait(kh_context *ctx, uint64_t ticket, kh_result *res);
+
+/* Withdraw a request that is still queued (not yet admitted): KH_OK and the
+ * ticket is retired; KH_EBUSY once it runs or has finished (collect it);
+ * KH_ENOTFOUND for unknown tickets. */
+kh_status kh_serve_cancel(kh_context *ctx, uint64_t ticket);
 
 /* Finish every queued request, stop the workers and drop uncollected results.
  * No call may wait on this context meanwhile.  kh_context_destroy does this too. */

@@ -51,7 +51,7 @@ struct Server {
     int running = 0;
     bool stopping = false;
     int queue_cap = 65536;
-    int64_t batch_vertices = 4 << 20;
+    int64_t batch_vertices = 1 << 20;
     uint64_t next_id = 1;
 };
 
@@ -336,6 +336,22 @@ extern "C" kh_status kh_serve_wait(kh_context* ctx, uint64_t ticket, kh_result* 
     Server* S = find_server(ctx);
     if (!S) return KH_ENOTFOUND;
     return collect(S, ticket, res, true);
+}
+
+extern "C" kh_status kh_serve_cancel(kh_context* ctx, uint64_t ticket) {
+    if (!ctx) return KH_EINVAL;
+    Server* S = find_server(ctx);
+    if (!S) return KH_ENOTFOUND;
+    std::lock_guard<std::mutex> lk(S->m);
+    auto it = S->table.find(ticket);
+    if (it == S->table.end()) return KH_ENOTFOUND;
+    Request* r = it->second;
+    auto q = std::find(S->queue.begin(), S->queue.end(), r);
+    if (q == S->queue.end()) return KH_EBUSY;  // running or finished: collect it instead
+    S->queue.erase(q);
+    S->table.erase(it);
+    delete r;
+    return KH_OK;
 }
 
 extern "C" kh_status kh_serve_stop(kh_context* ctx) {

@@ -38,7 +38,8 @@ KH_OUT_DEVICE = 8
 EXPORTED = [
     "kh_status_str", "kh_buffer_size", "kh_validate_csr", "kh_context_create", "kh_context_destroy",
     "kh_graph_load_csr", "kh_graph_free", "kh_graph_n", "kh_graph_nnz", "kh_core", "kh_core_batch", "kh_hdeg",
-    "kh_ranks", "kh_serve_start", "kh_serve_submit", "kh_serve_poll", "kh_serve_wait", "kh_serve_stop",
+    "kh_ranks", "kh_serve_start", "kh_serve_submit", "kh_serve_poll", "kh_serve_wait", "kh_serve_cancel",
+    "kh_serve_stop",
     "kh_sampled_lists", "kh_dense", "kh_profile_enable", "kh_profile_read",
 ]
 
@@ -107,6 +108,8 @@ def lib():
         L.kh_serve_poll.restype = i32
         L.kh_serve_wait.argtypes = [P, u64, ctypes.POINTER(Result)]
         L.kh_serve_wait.restype = i32
+        L.kh_serve_cancel.argtypes = [P, u64]
+        L.kh_serve_cancel.restype = i32
         L.kh_serve_stop.argtypes = [P]
         L.kh_serve_stop.restype = i32
         L.kh_hdeg.argtypes = [P, i32, P, u32, P, ctypes.POINTER(i64), P]
@@ -334,6 +337,16 @@ class Server:
 
     def wait(self, ticket: int):
         return self._collect(ticket, True)
+
+    def cancel(self, ticket: int) -> bool:
+        """True if the request was still queued and is withdrawn; False if it
+        already runs or has finished (collect it with poll / wait)."""
+        code = lib().kh_serve_cancel(self.ctx.handle, ticket)
+        if code == KH_EBUSY:
+            return False
+        _check(code, "kh_serve_cancel")
+        self._pending.pop(ticket, None)
+        return True
 
     def stop(self):
         _check(lib().kh_serve_stop(self.ctx.handle), "kh_serve_stop")

@@ -100,6 +100,24 @@ def test_serve_ticket_protocol(ctx):
         with pytest.raises(kh.KhError) as e:
             srv.submit(G, 0)
         assert e.value.code == -1
+        # withdrawing: unknown tickets are not found; a queued request may be
+        # withdrawn, a running or finished one must be collected
+        with pytest.raises(kh.KhError) as e:
+            srv.cancel(987654321)
+        assert e.value.code == kh.khcore.KH_ENOTFOUND
+        big = gg.barabasi_albert(20000, 3, seed=5)
+        GB = kh.Graph.from_gg(ctx, big)
+        t1 = srv.submit(GB, 3)
+        t2 = srv.submit(GB, 3)
+        t3 = srv.submit(G, 2, epsilon=0.5, seed=1)
+        for t in (t2, t3):
+            if srv.cancel(t):
+                with pytest.raises(kh.KhError) as e:
+                    srv.poll(t)
+                assert e.value.code == kh.khcore.KH_ENOTFOUND
+            else:
+                assert srv.wait(t)[0].size > 0
+        srv.wait(t1)
         # a second start on a serving context is refused
         with pytest.raises(kh.KhError) as e:
             kh.Server(ctx)
