@@ -201,7 +201,8 @@ void launch_compact_alive(const uint8_t* alive, int32_t n, int32_t* out, int* co
 }
 
 // ---- round bookkeeping ------------------------------------------------------------------
-__global__ void k_round_reset(RoundState* st) {
+__global__ void k_round_reset(RoundState* st, int gate) {
+    if (gate && st->stall) return;
     st->min_key = LLONG_MAX;
     st->sum_val = 0;
     st->alive_count = 0;
@@ -222,13 +223,15 @@ __global__ void k_round_reset(RoundState* st) {
     st->fcount[1] = 0;
     st->epoch += 1;
 }
-void launch_round_reset(RoundState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, s, st);
+void launch_round_reset(RoundState* st, hipStream_t s, int gate) {
+    hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, s, st, gate);
 }
 
 // min of key, sum of val and count over alive vertices (one atomic triple per block).
 __global__ __launch_bounds__(512) void k_reduce(const int64_t* __restrict__ key, const int64_t* __restrict__ val,
-                                                const uint8_t* __restrict__ alive, int32_t n, RoundState* st) {
+                                                const uint8_t* __restrict__ alive, int32_t n, RoundState* st,
+                                                int gate) {
+    if (gate && st->stall) return;
     __shared__ long long smin[8], ssum[8];
     __shared__ int scnt[8];
     long long mn = LLONG_MAX, sm = 0;
@@ -265,8 +268,9 @@ __global__ __launch_bounds__(512) void k_reduce(const int64_t* __restrict__ key,
     }
 }
 void launch_reduce(const int64_t* key, const int64_t* val, const uint8_t* alive, int32_t n, RoundState* st,
-                   hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_reduce, dim3(grid_for(n, 512, 256)), dim3(512), 0, s, key, val, alive, n, st);
+                   hipStream_t s, int gate) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_reduce, dim3(grid_for(n, 512, 256)), dim3(512), 0, s, key, val, alive, n, st, gate);
 }
 
 // c = max(c, min key).  When c rises to K, the alive set is exactly
@@ -685,7 +689,8 @@ __device__ __forceinline__ long long cur_level(const RoundState* st) {
 // shist (nullable, packed unions): the same per segment, shist[seg * 48 + b].
 __global__ void k_bound_hist(const uint8_t* __restrict__ alive, const int64_t* __restrict__ deg,
                              const uint8_t* __restrict__ exact, int32_t n, RoundState* st,
-                             const int32_t* __restrict__ seg, int* __restrict__ shist) {
+                             const int32_t* __restrict__ seg, int* __restrict__ shist, int gate) {
+    if (gate && st->stall) return;
     __shared__ int h[48];
     __shared__ int hs[48];  // segment histogram of the block's first vertex of the step
     if (threadIdx.x < 48) h[threadIdx.x] = 0;
@@ -719,10 +724,10 @@ __global__ void k_bound_hist(const uint8_t* __restrict__ alive, const int64_t* _
     if (threadIdx.x < 48 && h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
 }
 void launch_bound_hist(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
-                       hipStream_t s, const int32_t* seg, int* shist) {
+                       hipStream_t s, const int32_t* seg, int* shist, int gate) {
     if (n > 0)
         hipLaunchKernelGGL(k_bound_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, alive, deg, exact, n, st, seg,
-                           shist);
+                           shist, gate);
 }
 
 // Per segment of a packed union: the bound threshold of its next sources, chosen
@@ -757,7 +762,7 @@ void launch_decide_seg(RoundState* st, int nseg, int* shist, long long* shi, int
 
 // Commit the round when no inexact vertex is at or below c'; otherwise recompute
 // the cap inexact vertices with the smallest bounds (whole buckets).
-__global__ void k_decide(RoundState* st, int cap) {
+__device__ __forceinline__ void decide_round(RoundState* st, int cap) {
     if (st->alive_count == 0) {
         st->mode = 2;
         return;
@@ -776,9 +781,21 @@ __global__ void k_decide(RoundState* st, int cap) {
     }
     st->hi = B == 0 ? c : c + ((1ll << B) - 1);
 }
+__global__ void k_decide(RoundState* st, int cap) { decide_round(st, cap); }
 void launch_decide(RoundState* st, int cap, hipStream_t s) {
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(1), 0, s, st, cap);
 }
+
+__global__ void k_decide_commit(RoundState* st, int cap) {
+    if (st->stall) return;
+    decide_round(st, cap);
+    if (st->mode == 1) st->stall = 1;
+}
+void launch_decide_commit(RoundState* st, int cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide_commit, dim3(1), dim3(1), 0, s, st, cap);
+}
+__global__ void k_unstall(RoundState* st) { st->stall = 0; }
+void launch_unstall(RoundState* st, hipStream_t s) { hipLaunchKernelGGL(k_unstall, dim3(1), dim3(1), 0, s, st); }
 
 __global__ void k_pick(const uint8_t* __restrict__ alive, const int64_t* __restrict__ deg,
                        const uint8_t* __restrict__ exact, int32_t n, RoundState* st, int32_t* __restrict__ out,
@@ -860,6 +877,36 @@ void launch_select_gated(const int64_t* key, uint8_t* alive, int32_t n, RoundSta
                            rlist, mark, epoch);
 }
 
+__global__ void k_select_commit(const int64_t* __restrict__ key, uint8_t* __restrict__ alive, int32_t n,
+                                RoundState* st, int64_t* __restrict__ core, int32_t* __restrict__ rlist,
+                                int32_t* __restrict__ mark) {
+    if (st->mode != 0 || st->stall) return;
+    const int32_t epoch = st->epoch;
+    // every block computes the same level; block 0 records it
+    const long long c = cur_level(st);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->c = c;
+        st->rounds += 1;
+    }
+    const int32_t stride = gridDim.x * blockDim.x;
+    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int32_t v = base + threadIdx.x;
+        const bool take = v < n && alive[v] && key[v] <= c;
+        const int slot = wave_append_slot(take, &st->rcount);
+        if (take) {
+            core[v] = c;
+            rlist[slot] = v;
+            mark[v] = epoch;
+        }
+    }
+}
+void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core,
+                          int32_t* rlist, int32_t* mark, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_select_commit, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, key, alive, n, st, core,
+                           rlist, mark);
+}
+
 // ---- R-mask BFS of the lazy exact peel ---------------------------------------------------------
 // For v at distance exactly h from R, every vertex that leaves N(v;h,X) when R is
 // deleted is itself in R (a path that needed R reaches it after h steps), so
@@ -873,6 +920,12 @@ __global__ void k_rbfs_init(const int32_t* __restrict__ rlist, RoundState* st, u
         const unsigned long long b = 1ull << (j & 63);
         atomicOr((unsigned long long*)&rmask[r], b);
         atomicOr((unsigned long long*)&gain[r], b);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // resets of hop 1 (no thread of this kernel reads them)
+        st->fepoch += 1;
+        st->qcount = 0;
+        st->fcount[1] = 0;
     }
 }
 void launch_rbfs_init(const int32_t* rlist, RoundState* st, uint64_t* rmask, uint64_t* gain, hipStream_t s) {
@@ -937,6 +990,32 @@ void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount,
                         int32_t* alist, int* aff_fill, RoundState* st, hipStream_t s) {
     hipLaunchKernelGGL(k_rbfs_expand, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, gain_cur, rmask,
                        gain_next, mark, epoch, fmark, fepoch, fnext, fnext_count, alist, aff_fill, st);
+}
+
+__global__ void k_hop_end(RoundState* st, int* hopfill, int t, int h) {
+    hopfill[t] = st->aff_fill;
+    st->qcount = 0;
+    if (t < h) {
+        st->fepoch += 1;
+        st->fcount[(t + 1) & 1] = 0;
+    }
+}
+void launch_hop_end(RoundState* st, int* hopfill, int t, int h, hipStream_t s) {
+    hipLaunchKernelGGL(k_hop_end, dim3(1), dim3(1), 0, s, st, hopfill, t, h);
+}
+
+__global__ void k_clear_u64_lists3(const int32_t* __restrict__ l0, const int* c0, uint64_t* __restrict__ a0,
+                                   const int32_t* __restrict__ l1, const int* c1, uint64_t* __restrict__ a1,
+                                   const int32_t* __restrict__ l2, const int* c2, uint64_t* __restrict__ a2) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
+    const int n0 = *c0, n1 = *c1, n2 = *c2;
+    for (int i = tid; i < n0; i += nth) a0[l0[i]] = 0ull;
+    for (int i = tid; i < n1; i += nth) a1[l1[i]] = 0ull;
+    for (int i = tid; i < n2; i += nth) a2[l2[i]] = 0ull;
+}
+void launch_clear_u64_lists3(const int32_t* l0, const int* c0, uint64_t* a0, const int32_t* l1, const int* c1,
+                             uint64_t* a1, const int32_t* l2, const int* c2, uint64_t* a2, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_u64_lists3, dim3(512), dim3(256), 0, s, l0, c0, a0, l1, c1, a1, l2, c2, a2);
 }
 
 __global__ void k_clear_u64_list(const int32_t* __restrict__ list, const int* count, uint64_t* __restrict__ arr) {

@@ -643,6 +643,7 @@ struct Planes {
         P.sbit = seg ? sbit.p : nullptr;
         P.gcnt = seg ? gcnt.p : nullptr;
         P.ns_cap = seg ? ns_cap : 64 * q;
+        P.exact_out = nullptr;
         P.cvA = cvA.p;
         P.cvB = cvB.p;
         P.ciA = ciA.p;
@@ -705,14 +706,15 @@ bool graphs_off() {
 // issuing the launches directly.
 struct Replay {
     hipStream_t gs = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    std::vector<hipGraph_t> graphs;
+    std::vector<hipGraphExec_t> execs;
     bool direct = false;
     ~Replay() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : execs) (void)hipGraphExecDestroy(e);
+        for (auto g : graphs) (void)hipGraphDestroy(g);
         if (gs) (void)hipStreamDestroy(gs);
     }
+    // The stream, ordered after the caller's, and the first sequence (index 0).
     template <typename F>
     hipStream_t prepare(hipStream_t caller, bool use_graph, F&& record) {
         hip_ok(hipStreamCreate(&gs));
@@ -722,18 +724,29 @@ struct Replay {
         hip_ok(hipStreamWaitEvent(gs, ev, 0));
         hip_ok(hipEventDestroy(ev));
         direct = !use_graph;
-        if (!direct) {
-            hip_ok(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
-            record(gs);
-            hip_ok(hipStreamEndCapture(gs, &graph));
-            hip_ok(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        }
+        add(record);
         return gs;
     }
+    // Another sequence on the same stream (next index).
     template <typename F>
-    void run(F&& record) {
+    int add(F&& record) {
+        if (!direct) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t e = nullptr;
+            hip_ok(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+            record(gs);
+            hip_ok(hipStreamEndCapture(gs, &g));
+            graphs.push_back(g);
+            hip_ok(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+            execs.push_back(e);
+            return (int)execs.size() - 1;
+        }
+        return 0;
+    }
+    template <typename F>
+    void run(F&& record, int index = 0) {
         if (direct) record(gs);
-        else hip_ok(hipGraphLaunch(exec, gs));
+        else hip_ok(hipGraphLaunch(execs[(size_t)index], gs));
     }
 };
 
@@ -840,24 +853,25 @@ struct ExactRun {
 
     // Deletion tail of the lazy peel: mask BFS from R over h hops (R still alive),
     // remove R, update alive degrees.  Leaves alist/hopfill/rmask for the decay step.
-    void delete_round_masked(int32_t epoch) {
+    // The deletion of the commit sequence: mask BFS from R (|R| <= 64 gives the
+    // exact decrement of the vertices at distance exactly h), R leaves X, the
+    // alive degrees drop.  Every list count it reads is zero when no round was
+    // committed.
+    void delete_round_masked() {
         launch_rbfs_init(rlist.p, st.p, rmask.p, gainA.p, s);
         int32_t* fl[2] = {flA.p, flB.p};
         uint64_t* gain[2] = {gainA.p, gainB.p};
         for (int t = 1; t <= h; ++t) {
             const int32_t* src = t == 1 ? rlist.p : fl[(t - 1) & 1];
             const int* srcn = t == 1 ? &st.p->rcount : &st.p->fcount[(t - 1) & 1];
-            launch_rbfs_hop_reset(st.p, t, s);
             launch_enqueue(src, nullptr, srcn, g->rp, qv.p, qb.p, &st.p->qcount, s);
             launch_rbfs_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, gain[(t - 1) & 1], rmask.p,
-                               gain[t & 1], mark.p, epoch, fmark.p, -1, fl[t & 1], &st.p->fcount[t & 1], alist.p,
+                               gain[t & 1], mark.p, -1, fmark.p, -1, fl[t & 1], &st.p->fcount[t & 1], alist.p,
                                &st.p->aff_fill, st.p, s);
             launch_clear_u64_list(src, srcn, gain[(t - 1) & 1], s);
-            launch_record_fill(st.p, hopfill.p, t, s);
+            launch_hop_end(st.p, hopfill.p, t, h, s);
         }
-        launch_clear_u64_list(fl[h & 1], &st.p->fcount[h & 1], gain[h & 1], s);
         launch_kill_list(rlist.p, &st.p->rcount, alive.p, s);
-        launch_set_int(&st.p->qcount, 0, s);
         launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
         launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, 0, 1, nullptr, nullptr, adeg.p, s);
     }
@@ -910,50 +924,71 @@ struct ExactRun {
             shi.alloc(ctx, (size_t)g->nseg);
             hip_ok(hipMemsetAsync(shist.p, 0, shist.count * sizeof(int), s));
         }
-        // Each iteration is one fixed kernel sequence: count the inexact vertices
-        // by (bound - c'), then either recompute the smallest bounds (up to 64 Q
-        // sources, at least every one at or below c') or commit the round.  Every
-        // kernel reads the decision from device memory, so the host only checks
-        // for the end every few iterations.
-        const int per_sync = 32;
+        // Two fixed kernel sequences, replayed on one stream.  The commit
+        // sequence (iterated) counts the inexact vertices by (bound - c') and
+        // commits the round when none is at or below c'; otherwise it stalls
+        // and its remaining kernels do nothing.  The recompute sequence then
+        // recomputes the smallest bounds (up to 64 Q sources, per graph of a
+        // packed union) and lifts the stall.  Every kernel reads its decision
+        // from device memory, so the host only checks every few iterations.
         const hipStream_t caller = s;
         Replay rp;
-        auto record = [&](hipStream_t q) {
+        int32_t* fl[2] = {flA.p, flB.p};
+        uint64_t* gain[2] = {gainA.p, gainB.p};
+        auto commit_body = [&](hipStream_t q, int iters_per) {
             const hipStream_t keep = s;
             s = q;
-            const MsPlanes P = PL.view(PL.qmax);
-            for (int r = 0; r < per_sync; ++r) {
-                launch_round_reset(st.p, s);
-                launch_reduce(deg.p, nullptr, alive.p, n, st.p, s);
-                launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, s, g->seg, shist.p);
-                launch_decide(st.p, qbits, s);
-                if (g->seg) launch_decide_seg(st.p, g->nseg, shist.p, shi.p, qbits, s);
-                launch_pick(alive.p, deg.p, exact.p, n, st.p, srcl.p, cap, s, g->seg, PL.gcnt.p, PL.sbit.p, qbits,
-                            g->seg ? shi.p : nullptr);
-                ms_batch(P, g->items, n, g->rp, g->col, alive.p, adeg.p, srcl.p, 0, &st.p->ms_ns, h, deg.p, st.p, s);
-                launch_mark_exact(srcl.p, st.p, exact.p, s);
-                launch_round_begin_gated(st.p, s);
-                launch_select_gated(deg.p, alive.p, n, st.p, core.p, rlist.p, mark.p, -1, s);
-                delete_round_masked(-1);
+            for (int r = 0; r < iters_per; ++r) {
+                launch_round_reset(st.p, s, 1);
+                launch_reduce(deg.p, nullptr, alive.p, n, st.p, s, 1);
+                launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, s, nullptr, nullptr, 1);
+                launch_decide_commit(st.p, qbits, s);
+                launch_select_commit(deg.p, alive.p, n, st.p, core.p, rlist.p, mark.p, s);
+                delete_round_masked();
                 launch_anchor(alist.p, &st.p->aff_fill, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 1, s);
                 launch_decay_masked(alist.p, st.p, hopfill.p, h, alive.p, adeg.p, anchor.p, rmask.p, deg.p, exact.p,
                                     s);
-                launch_clear_u64_list(alist.p, &st.p->aff_fill, rmask.p, s);
-                launch_clear_u64_list(rlist.p, &st.p->rcount, rmask.p, s);
+                launch_clear_u64_lists3(fl[h & 1], &st.p->fcount[h & 1], gain[h & 1], alist.p, &st.p->aff_fill,
+                                        rmask.p, rlist.p, &st.p->rcount, rmask.p, s);
             }
             s = keep;
         };
+        const int long_iters = 32, short_iters = 4;
+        auto record_long = [&](hipStream_t q) { commit_body(q, long_iters); };
+        auto record_short = [&](hipStream_t q) { commit_body(q, short_iters); };
+        auto record_recompute = [&](hipStream_t q) {
+            MsPlanes P = PL.view(PL.qmax);
+            P.exact_out = exact.p;
+            if (g->seg) {
+                launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, q, g->seg, shist.p, 0);
+                launch_decide_seg(st.p, g->nseg, shist.p, shi.p, qbits, q);
+            }
+            launch_pick(alive.p, deg.p, exact.p, n, st.p, srcl.p, cap, q, g->seg, PL.gcnt.p, PL.sbit.p, qbits,
+                        g->seg ? shi.p : nullptr);
+            ms_batch(P, g->items, n, g->rp, g->col, alive.p, adeg.p, srcl.p, 0, &st.p->rc_count, h, deg.p, st.p, q);
+            launch_unstall(st.p, q);
+        };
         const bool use_graph = !graphs_off() && !prof_active(ctx);
         PL.timer = prof_active(ctx) ? &ctx->timer[0] : nullptr;
-        const hipStream_t q = rp.prepare(caller, use_graph, record);
+        const hipStream_t q = rp.prepare(caller, use_graph, record_long);
+        const int i_short = rp.add(record_short);
+        const int i_rec = rp.add(record_recompute);
+        bool stalled = false;
         for (;;) {
-            rp.run(record);
+            if (stalled) {
+                rp.run(record_recompute, i_rec);
+                rp.run(record_short, i_short);
+                iters += short_iters + 1;
+            } else {
+                rp.run(record_long, 0);
+                iters += long_iters;
+            }
             if (prof_active(ctx)) prof_collect(ctx);
-            iters += per_sync;
             read_state(ctx, st.p, q);
             const RoundState hs = *hstate(ctx);
             if (hs.mode == 2) break;
-            if (iters > 4ll * n + 4096) fail(KH_EDEVICE);
+            stalled = hs.stall != 0;
+            if (iters > 8ll * n + 4096) fail(KH_EDEVICE);
             if (hs.fepoch > (1 << 30)) {
                 // frontier marks are compared for equality only: restart their epochs
                 launch_fill_i32(fmark.p, 0, n, q);

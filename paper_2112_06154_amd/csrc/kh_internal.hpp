@@ -61,6 +61,8 @@ struct RoundState {
     int epoch;               // device-side mark epoch (advanced by the round / level resets)
     int fepoch;              // device-side frontier-mark epoch (advanced per mask-BFS hop)
     int overflow;            // an estimate exceeded the representable range
+    int stall;               // lazy exact peel: a commit sequence waits for exact recomputations
+    int pad_stall;
     unsigned long long te;     // edges traversed (exact h-degree work)
     unsigned long long arcs;   // adjacency entries read by the h-degree kernels
     unsigned long long elems;  // sample-list entries read by the union kernels
@@ -98,9 +100,9 @@ void launch_alive_from(const uint8_t* src, uint8_t* alive, int32_t n, hipStream_
 void launch_alive_degree(const int32_t* rp, const int32_t* col, const uint8_t* alive, int32_t* adeg, int32_t n,
                          hipStream_t s);
 void launch_compact_alive(const uint8_t* alive, int32_t n, int32_t* out, int* count, hipStream_t s);
-void launch_round_reset(RoundState* st, hipStream_t s);
+void launch_round_reset(RoundState* st, hipStream_t s, int gate = 0);
 void launch_reduce(const int64_t* key, const int64_t* val, const uint8_t* alive, int32_t n, RoundState* st,
-                   hipStream_t s);
+                   hipStream_t s, int gate = 0);
 void launch_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_size, int64_t* cand_sum, int early_stop,
                         hipStream_t s);
 void launch_select(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core, int32_t* rlist,
@@ -141,8 +143,22 @@ void launch_lazy_candidates(const uint8_t* alive, const int64_t* deg, const uint
 void launch_set_flags(const int32_t* list, int count, uint8_t* flags, uint8_t v, hipStream_t s);
 // device-driven exact peel steps
 void launch_bound_hist(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
-                       hipStream_t s, const int32_t* seg = nullptr, int* shist = nullptr);
+                       hipStream_t s, const int32_t* seg = nullptr, int* shist = nullptr, int gate = 0);
 void launch_decide(RoundState* st, int cap, hipStream_t s);
+// The commit sequence of the lazy exact peel: as launch_decide, but a needed
+// recomputation stalls the sequence (st->stall) instead of picking sources;
+// the gated kernels of the sequence then do nothing until launch_unstall.
+void launch_decide_commit(RoundState* st, int cap, hipStream_t s);
+void launch_unstall(RoundState* st, hipStream_t s);
+// Round begin folded into the selection: c = max(c, min key), rounds += 1.
+void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core,
+                          int32_t* rlist, int32_t* mark, hipStream_t s);
+// Mask BFS bookkeeping of hop t: hopfill[t] = aff_fill, then the resets of hop
+// t + 1 (t < h) or the expansion queue (t == h).
+void launch_hop_end(RoundState* st, int* hopfill, int t, int h, hipStream_t s);
+// arr_k[list_k[i]] = 0 for three (list, count, array) triples at once.
+void launch_clear_u64_lists3(const int32_t* l0, const int* c0, uint64_t* a0, const int32_t* l1, const int* c1,
+                             uint64_t* a1, const int32_t* l2, const int* c2, uint64_t* a2, hipStream_t s);
 // Picks the inexact alive vertices with deg <= st->hi as the next sources (at
 // most cap).  seg (nullable): segment (graph) of every vertex of a packed union;
 // then each source also gets a bit position sbit[slot] that is unique within its
@@ -218,6 +234,7 @@ struct MsPlanes {
     const int32_t* sbit;  // nullable: bit position of source j (else j)
     int* gcnt;            // per-segment pick counters (reset by the scatter)
     int ns_cap;           // most sources of one batch (64 Q, or n when segmented)
+    uint8_t* exact_out;   // nullable: exact_out[source] = 1 (its h-degree is now exact)
     uint64_t* valid;      // Q words: bits of the batch's sources
     PullTimer* timer;     // nullable
 };

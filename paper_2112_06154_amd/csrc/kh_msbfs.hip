@@ -49,11 +49,13 @@ template <int Q>
 __global__ void k_ms_init(const int32_t* __restrict__ src, int ns, const int* ns_dev, int ns_cap,
                           const int32_t* __restrict__ sbit, const int32_t* __restrict__ seg,
                           uint64_t* __restrict__ vis, const int32_t* __restrict__ adeg, uint64_t* __restrict__ valid,
-                          RoundState* st, MsCtl* ctl, int32_t* __restrict__ tl, uint32_t* __restrict__ bmTile) {
+                          RoundState* st, MsCtl* ctl, int32_t* __restrict__ tl, uint32_t* __restrict__ bmTile,
+                          uint8_t* __restrict__ exact_out) {
     if (ns_dev) ns = min(*ns_dev, ns_cap);
     unsigned long long te = 0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ns; j += gridDim.x * blockDim.x) {
         const int32_t s = src[j];
+        if (exact_out) exact_out[s] = 1;
         const int bj = sbit ? sbit[j] : j;
         vis[(size_t)s * Q + (bj >> 6)] = 1ull << (bj & 63);
         te += (unsigned long long)adeg[s];
@@ -569,7 +571,7 @@ static void ms_batch_q(const MsPlanes& P, const MsItems& I, int32_t n, const int
     int32_t* ci[2] = {P.ciA, P.ciB};
     int2* fc[2] = {P.fcA, P.fcB};
     hipLaunchKernelGGL(k_ms_init<Q>, dim3(grid_for(nsg, 256, 64)), dim3(256), 0, s, src, ns, ns_dev, ns_cap, P.sbit,
-                       P.seg, P.vis, adeg, P.valid, st, P.ctl, P.tl, P.bmTile);
+                       P.seg, P.vis, adeg, P.valid, st, P.ctl, P.tl, P.bmTile, P.exact_out);
     // hop 1: push
     hipLaunchKernelGGL(k_ms_push<Q>, dim3(grid_for((int64_t)nsg * 64, 256, 4096)), dim3(256), 0, s, src, ns, ns_dev,
                        ns_cap, P.sbit, rp, col, alive, P.acc, P.bmT, P.touched, P.touched_count, st);
