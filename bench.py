@@ -242,6 +242,63 @@ def bench_serve(kh, ctx, args):
                               "p99_ms": round(1e3 * percentile(v, 99), 3)} for k, v in sorted(cls.items())}}
 
 
+def bench_cl4m(kh, ctx, args):
+    """Large power-law workload (Chung-Lu n = 4,000,000, m = 60,000,000,
+    gamma = 2.3): sampled Core at h = 3 for each epsilon in --cl4m-eps with the
+    densest-core estimate (Alg. 7, pruning variant); then the deviation of the
+    sampled core numbers from the exact ones on a smaller graph of the same
+    family (n = --dev-n, average degree 30), where ExactCore is affordable."""
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    out = {}
+    t0 = time.time()
+    g = gg.workload("cl4m")
+    log(f"cl4m generated in {time.time() - t0:.1f}s")
+    G = kh.Graph.from_gg(ctx, g)
+    core_out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    for eps in [float(x) for x in args.cl4m_eps.split(",")]:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, res = kh.core(G, 3, epsilon=eps, delta=0.05, seed=1, out=core_out, dense=True, prune=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        log(f"cl4m sampled h=3 eps={eps}: {dt:.1f}s")
+        out[f"eps{eps}"] = {"seconds": round(dt, 3), **{k: res[k] for k in (
+            "M_used", "M_dense_used", "rounds", "max_core", "dense_k", "dense_size", "dense_density",
+            "list_elements")}}
+    del G
+    # deviation from exact on a smaller graph of the same family
+    n = args.dev_n
+    gs = gg.chung_lu(n, 15 * n, 2.3, seed=2)
+    Gs = kh.Graph.from_gg(ctx, gs)
+    t = time.perf_counter()
+    ex, rex = kh.core(Gs, 3)
+    tex = time.perf_counter() - t
+    log(f"deviation graph n={n}: exact h=3 {tex:.1f}s")
+    dev = {"graph": f"chung_lu n={n} m={15 * n} gamma=2.3 seed=2", "h": 3, "exact_seconds": round(tex, 3),
+           "exact_rounds": rex["rounds"], "exact_max_core": rex["max_core"]}
+    exv = ex.astype(np.float64)
+    for eps in [float(x) for x in args.cl4m_eps.split(",")]:
+        t = time.perf_counter()
+        sc, rs = kh.core(Gs, 3, epsilon=eps, delta=0.05, seed=1)
+        ts = time.perf_counter() - t
+        pos = exv > 0
+        ratio = sc[pos].astype(np.float64) / exv[pos]
+        M = rs["M_used"]
+        dev[f"eps{eps}"] = {
+            "seconds": round(ts, 3), "M_used": M, "max_rel_dev": float(np.max(np.abs(ratio - 1.0))),
+            "mean_rel_dev": float(np.mean(np.abs(ratio - 1.0))),
+            "frac_within_eps": float(np.mean(np.abs(ratio - 1.0) <= eps)),
+            "frac_exact": float(np.mean(sc == ex)),
+            "frac_exact_where_core_lt_M": float(np.mean((sc == ex)[ex < M])) if np.any(ex < M) else None,
+            "frac_core_lt_M": float(np.mean(ex < M))}
+        log(f"deviation eps={eps}: {dev[f'eps{eps}']}")
+    out["deviation"] = dev
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,7 +321,10 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-grace", type=float, default=60.0,
                     help="seconds after the last arrival before queued requests are withdrawn")
-    ap.add_argument("--skip-main", action="store_true", help="only the --batch / --serve measurements")
+    ap.add_argument("--cl4m", action="store_true", help="also measure the 4M-vertex sampled workload")
+    ap.add_argument("--cl4m-eps", default="0.5,0.25")
+    ap.add_argument("--dev-n", type=int, default=100_000)
+    ap.add_argument("--skip-main", action="store_true", help="only the --batch / --serve / --cl4m measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -285,6 +345,8 @@ def main():
             extra["batch"] = bench_batch(kh, ctx, args)
         if args.serve:
             extra["serve"] = bench_serve(kh, ctx, args)
+        if args.cl4m:
+            extra["cl4m"] = bench_cl4m(kh, ctx, args)
         print(json.dumps(extra))
         return
     t0 = time.time()
@@ -391,6 +453,8 @@ def main():
         line["batch"] = bench_batch(kh, ctx, args)
     if args.serve:
         line["serve"] = bench_serve(kh, ctx, args)
+    if args.cl4m:
+        line["cl4m"] = bench_cl4m(kh, ctx, args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, hs, args.cpu_budget)
     print(json.dumps(line))
