@@ -130,7 +130,9 @@ int64_t kh_graph_nnz(const kh_graph *g);
  * densest core level (Sec. 6; for epsilon > 0 its sum uses fresh ranks from
  * stream 1 and M from C = log(n^2/delta), Alg. 7).  res may be NULL.
  * Errors: KH_EINVAL (h < 1, delta outside (0,1), NULL core_out with n > 0),
- * KH_ENOTIMPL (sampled path with n >= 2^24 or integer M > 7935),
+ * KH_ENOTIMPL (sampled path with n >= 2^24, or an integer M whose LDS hash set,
+ * 2 (M + 1025) entries rounded up to a power of two, does not fit one
+ * work-group's LDS next to ~17 KiB of other state: M <= 15,359 with 160 KiB),
  * KH_EOVERFLOW (core number above INT32_MAX), KH_ENOMEM, KH_EDEVICE. */
 kh_status kh_core(kh_graph *g, const kh_params *params, int32_t *core_out, kh_result *res, void *stream);
 

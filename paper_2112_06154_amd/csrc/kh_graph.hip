@@ -421,6 +421,7 @@ __global__ void k_level_reset(RoundState* st, int level) {
     st->qcount = 0;
     st->wl_count = 0;
     st->rc_count = 0;
+    st->hub_count = 0;
     st->changed_count[level & 1] = 0;
 }
 void launch_level_reset(RoundState* st, int level, hipStream_t s) {

@@ -1066,13 +1066,18 @@ struct Lists {
     }
 };
 
-int hash_log2_for(int32_t M) { return std::max(9, ceil_log2(2ll * ((long long)M + 1 + kUnionThreads))); }
+// The union kernel's LDS hash set may exceed M by one entry per thread of the
+// block (every thread can pass the "count <= M" test before any insert lands)
+// plus the vertex itself; twice that bound keeps the load factor <= 1/2, so
+// every probe sequence ends.  The widest block (hubs) sets the size.
+int hash_log2_for(int32_t M) { return std::max(9, ceil_log2(2ll * ((long long)M + 1 + kUnionHubThreads))); }
 
 int32_t max_sampled_M(const kh_context* ctx) {
-    // dynamic LDS of the union kernel: 4 << hash_log2 bytes, plus ~1.1 KiB static
+    // dynamic LDS of the union kernel: 4 << hash_log2 bytes, plus ~17 KiB
+    // static for the widest block
     int l = 9;
-    while (l < 20 && ((size_t)4 << (l + 1)) + 2048 <= ctx->lds_per_block) ++l;
-    return (int32_t)((1ll << (l - 1)) - 1 - kUnionThreads);
+    while (l < 20 && ((size_t)4 << (l + 1)) + 20480 <= ctx->lds_per_block) ++l;
+    return (int32_t)((1ll << (l - 1)) - 1 - kUnionHubThreads);
 }
 
 struct SampledRun {
@@ -1088,7 +1093,7 @@ struct SampledRun {
     const int32_t* Mv = nullptr;
     const int32_t* lid = nullptr;
     Buf<uint8_t> alive, rank;
-    Buf<int32_t> mark, rlist, wl, rc, lostmax, chA, chB, qv, qb, cursor, order;
+    Buf<int32_t> mark, rlist, wl, rc, hubs, lostmax, chA, chB, qv, qb, cursor, order;
     Buf<int64_t> d, core, ck, cs, cr, partials;
     Buf<RoundState> st;
     Lists L;
@@ -1104,6 +1109,7 @@ struct SampledRun {
         rlist.alloc(ctx, n);
         wl.alloc(ctx, n);
         rc.alloc(ctx, n);
+        hubs.alloc(ctx, n);
         lostmax.alloc(ctx, n);
         chA.alloc(ctx, n);
         chB.alloc(ctx, n);
@@ -1213,14 +1219,16 @@ struct SampledRun {
                                        qb.p, &st.p->qcount, q);
                     launch_expand_lists(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, rank.p, mark.p, -1, i,
                                         L.view(i - 1), L.view(i), lostmax.p, wl.p, &st.p->wl_count, st.p, q);
-                    launch_classify(wl.p, &st.p->wl_count, L.view(i), lostmax.p, rc.p, &st.p->rc_count, q);
+                    // levels >= 2: hubs are merged by the wide-block variant of the union kernel
+                    launch_classify(wl.p, &st.p->wl_count, L.view(i), lostmax.p, rc.p, &st.p->rc_count, q, g->rp,
+                                    i > 1 ? hubs.p : nullptr, &st.p->hub_count);
                     if (i == 1)
                         launch_union1(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.view(1),
                                       changed[1], &st.p->changed_count[1], st.p, q);
                     else
                         launch_union(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.hash_log2,
                                      L.view(i - 1), L.view(i), cursor.p, order.p, changed[i & 1],
-                                     &st.p->changed_count[i & 1], st.p, q, utimer);
+                                     &st.p->changed_count[i & 1], st.p, q, utimer, hubs.p, &st.p->hub_count);
                 }
                 launch_estimate(changed[h & 1], &st.p->changed_count[h & 1], n, alive.p, rank.p, L.size[h].p,
                                 L.kk[h].p, M, Mv, d.p, st.p, q);

@@ -28,13 +28,10 @@ constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 // Threads of a union work-group and the largest hash table (entries) that fits
 // the LDS budget of one work-group.
 constexpr int kUnionThreads = 256;
+// block size of the union kernel for hubs (more than kHubDegree neighbours)
+constexpr int kUnionHubThreads = 1024;
 // Vertices with more neighbours than this order their arcs by list head rank in the union.
 constexpr int kHubDegree = 1024;
-constexpr int kMaxHashLog2 = 14;  // 16384 entries = 64 KiB
-
-// Largest integer M the sampled path accepts: the per-vertex LDS hash table
-// holds 2 (M + 1 + kUnionThreads) entries.
-constexpr int32_t kMaxM = (1 << (kMaxHashLog2 - 1)) - 1 - kUnionThreads;
 
 // Per-run device state for the bulk peeling rounds (one instance in device memory).
 struct RoundState {
@@ -52,6 +49,8 @@ struct RoundState {
     int wl_count;            // union worklist fill
     int changed_count[2];    // vertices whose (k, B) changed (ping-pong by level parity)
     int rc_count;            // worklist vertices that must be re-merged / recomputed
+    int hub_count;           // the hubs among them (sampled peel: merged by wider blocks)
+    int pad_hub;
     int opt_count;           // optional recomputations appended to a batch
     int mode;                // device-driven exact peel: 0 commit, 1 recompute, 2 done
     int ms_ns;               // sources of the current device-driven h-degree batch
@@ -284,7 +283,8 @@ void launch_union1(const int32_t* worklist, const int* wl_count, int32_t n, cons
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, int hash_log2,
                   LevelView prev, LevelView cur, int32_t* cursor, int32_t* order, int32_t* changed,
-                  int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer = nullptr);
+                  int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer = nullptr,
+                  const int32_t* hubs = nullptr, const int* hub_count = nullptr);
 // Propagate the deletions and changes of level i-1 over the arcs of the queued
 // vertices: mark + append alive neighbours, fold the highest lost rank into
 // lostmax[], and keep m[.,i] current.
@@ -293,8 +293,11 @@ void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount
                          int level, LevelView prev, LevelView cur, int32_t* lostmax, int32_t* out, int* out_count,
                          RoundState* st, hipStream_t s);
 // Keep only the worklist vertices whose list can change.
+// hubs (nullable): vertices with more than kHubDegree neighbours that need a
+// re-merge go to this list instead of rc.
 void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int32_t* lostmax, int32_t* rc,
-                     int* rc_count, hipStream_t s);
+                     int* rc_count, hipStream_t s, const int32_t* rp = nullptr, int32_t* hubs = nullptr,
+                     int* hub_count = nullptr);
 // Alg. 1 estimate from level h.  worklist == NULL: all vertices.
 void launch_estimate(const int32_t* worklist, const int* wl_count, int32_t n, const uint8_t* alive,
                      const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, const int32_t* Mv,

@@ -21,6 +21,12 @@
 
 namespace kh {
 
+// Neighbour walks issue the loads of several arcs per thread before using any
+// of them, so that a block walking a hub keeps many random reads in flight.
+constexpr int kScanUnroll = 8;
+constexpr int kWideUnroll = 4;
+
+
 __device__ __forceinline__ uint32_t* keys_at(const LevelView& L, int32_t v) { return L.keys + L.off[v]; }
 
 // Packed per-list header: one 4-byte read instead of three scattered ones.
@@ -97,9 +103,19 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
             s_lost = -1;
         }
         __syncthreads();
-        for (int32_t p = b + tid; p < e; p += blockDim.x) {
-            const int32_t w = col[p];
-            if (alive[w]) atomicAdd(&hist[rank[w]], 1);
+        for (int32_t p0 = b + tid; p0 < e; p0 += (int32_t)blockDim.x * kScanUnroll) {
+            int32_t w[kScanUnroll];
+            int rw[kScanUnroll];
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+                const int32_t p = p0 + u * (int32_t)blockDim.x;
+                w[u] = p < e ? col[p] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) rw[u] = (w[u] >= 0 && alive[w[u]]) ? rank[w[u]] : -1;
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u)
+                if (rw[u] >= 0) atomicAdd(&hist[rw[u]], 1);
         }
         elems += (unsigned long long)((e - b + (int)blockDim.x - 1 - tid) / (int)blockDim.x);
         if (tid == 0) atomicAdd(&hist[rank[v]], 1);
@@ -142,12 +158,19 @@ __global__ __launch_bounds__(256) void k_union1(const int32_t* __restrict__ work
             if (lane_id() == 0 && lm >= 0) atomicMax(&s_lost, lm);
             __syncthreads();
         }
-        for (int32_t p = b + tid; p < e; p += blockDim.x) {
-            const int32_t w = col[p];
-            if (alive[w]) {
-                const int rw = rank[w];
-                if (rw >= k) out[atomicAdd(&hist[rw], 1)] = sample_key(rw, w);
+        for (int32_t p0 = b + tid; p0 < e; p0 += (int32_t)blockDim.x * kScanUnroll) {
+            int32_t w[kScanUnroll];
+            int rw[kScanUnroll];
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+                const int32_t p = p0 + u * (int32_t)blockDim.x;
+                w[u] = p < e ? col[p] : -1;
             }
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) rw[u] = (w[u] >= 0 && alive[w[u]]) ? rank[w[u]] : -1;
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u)
+                if (rw[u] >= k) out[atomicAdd(&hist[rw[u]], 1)] = sample_key(rw[u], w[u]);
         }
         if (tid == 0) {
             const int rv = rank[v];
@@ -214,7 +237,8 @@ __device__ __forceinline__ bool hs_contains(const HashSet& H, uint32_t key) {
     }
 }
 
-// Block-wide exclusive scan of one int per thread (blockDim.x == kUnionThreads).
+// Block-wide exclusive scan of one int per thread (blockDim.x == BS).
+template <int BS>
 __device__ __forceinline__ int block_excl_scan_i(int v, int* sh, int* total) {
     const int l = lane_id();
     const int w = threadIdx.x >> 6;
@@ -223,7 +247,7 @@ __device__ __forceinline__ int block_excl_scan_i(int v, int* sh, int* total) {
     __syncthreads();
     int off = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < kUnionThreads / 64; ++i) {
+    for (int i = 0; i < BS / 64; ++i) {
         if (i < w) off += sh[i];
         tot += sh[i];
     }
@@ -268,18 +292,19 @@ __device__ __forceinline__ int arc_run(const uint32_t* __restrict__ lst, ArcStat
     return len;
 }
 
+template <int BS>
 __device__ __forceinline__ void insert_runs(int len, long long seg, const LevelView& prev, const HashSet& H, int M,
                                             int* s_offs, long long* s_seg, int* s_scan,
                                             unsigned long long& elems, unsigned long long& bytes) {
     const int tid = threadIdx.x;
     s_seg[tid] = seg;
     int tot;
-    const int off = block_excl_scan_i(len, s_scan, &tot);
+    const int off = block_excl_scan_i<BS>(len, s_scan, &tot);
     s_offs[tid] = off;
     __syncthreads();
-    for (int j = tid; j < tot; j += kUnionThreads) {
+    for (int j = tid; j < tot; j += BS) {
         // the run holding entry j: last a with offs[a] <= j
-        int a = 0, z = kUnionThreads - 1;
+        int a = 0, z = BS - 1;
         while (a < z) {
             const int mid = (a + z + 1) >> 1;
             if (s_offs[mid] <= j) a = mid; else z = mid - 1;
@@ -296,39 +321,59 @@ __device__ __forceinline__ void insert_runs(int len, long long seg, const LevelV
 
 // Vertices with more than kUnionThreads neighbours: arcs in chunks, cursors in
 // global scratch (hubs visit only the arcs whose list head reaches lo).
+template <int BS>
 __device__ void union_pass_wide(int lo, int32_t b, int32_t span, bool hub, const int32_t* __restrict__ order,
                                 const int32_t* __restrict__ col, const uint8_t* __restrict__ alive,
                                 const LevelView& prev, int32_t* __restrict__ cursor, const HashSet& H, int M,
                                 int* s_offs, long long* s_seg, int* s_scan, unsigned long long& elems,
                                 unsigned long long& bytes) {
     const int tid = threadIdx.x;
-    for (int32_t c0 = 0; c0 < span; c0 += kUnionThreads) {
-        const int32_t i = c0 + tid;
-        int len = 0;
-        long long seg = 0;
-        if (i < span) {
-            const int32_t p = hub ? order[b + i] : b + i;
-            const int32_t w = col[p];
-            bytes += hub ? 9 : 5;
-            if (alive[w]) {
-                ArcState a;
-                a.size = meta_size(prev.meta[w]);
-                a.cur = cursor[p];
-                bytes += 8;
-                if (a.cur < a.size) {
-                    a.off = prev.off[w];
-                    bytes += 8;
-                    const int start = a.cur;
-                    len = arc_run(prev.keys + a.off, a, lo, bytes);
-                    if (len) {
-                        seg = a.off + start;
-                        cursor[p] = a.cur;
-                        bytes += 4;
-                    }
-                }
+    for (int32_t c0 = 0; c0 < span; c0 += BS * kWideUnroll) {
+        int32_t p[kWideUnroll], w[kWideUnroll];
+        ArcState a[kWideUnroll];
+#pragma unroll
+        for (int u = 0; u < kWideUnroll; ++u) {
+            const int32_t i = c0 + u * BS + tid;
+            p[u] = i < span ? (hub ? order[b + i] : b + i) : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < kWideUnroll; ++u) w[u] = p[u] >= 0 ? col[p[u]] : -1;
+#pragma unroll
+        for (int u = 0; u < kWideUnroll; ++u) {
+            a[u].size = 0;
+            a[u].cur = 0;
+            a[u].off = 0;
+            if (w[u] >= 0 && alive[w[u]]) {
+                a[u].size = meta_size(prev.meta[w[u]]);
+                a[u].cur = cursor[p[u]];
             }
         }
-        insert_runs(len, seg, prev, H, M, s_offs, s_seg, s_scan, elems, bytes);
+#pragma unroll
+        for (int u = 0; u < kWideUnroll; ++u)
+            if (a[u].cur < a[u].size) a[u].off = prev.off[w[u]];
+        int len[kWideUnroll];
+        long long seg[kWideUnroll];
+#pragma unroll
+        for (int u = 0; u < kWideUnroll; ++u) {
+            len[u] = 0;
+            seg[u] = 0;
+            if (w[u] < 0) continue;
+            bytes += hub ? 9 : 5;
+            if (!alive[w[u]]) continue;
+            bytes += 8;
+            if (a[u].cur >= a[u].size) continue;
+            bytes += 8;
+            const int start = a[u].cur;
+            len[u] = arc_run(prev.keys + a[u].off, a[u], lo, bytes);
+            if (len[u]) {
+                seg[u] = a[u].off + start;
+                cursor[p[u]] = a[u].cur;
+                bytes += 4;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kWideUnroll; ++u)
+            insert_runs<BS>(len[u], seg[u], prev, H, M, s_offs, s_seg, s_scan, elems, bytes);
     }
 }
 
@@ -341,7 +386,8 @@ __device__ void union_pass_wide(int lo, int32_t b, int32_t span, bool hub, const
 // above and the old list held every member of rank >= old k, at most M of
 // them; removing vertices only shrinks N(v;i).  So all entries of rank >= old k
 // are inserted in one pass, and the level-by-level search only runs below it.
-__global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ worklist, const int* wl_count, int32_t n,
+template <int BS>
+__global__ __launch_bounds__(BS) void k_union(const int32_t* __restrict__ worklist, const int* wl_count, int32_t n,
                                                const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                const uint8_t* __restrict__ alive, const uint8_t* __restrict__ rank,
                                                int32_t M0, const int32_t* __restrict__ Mv, int hash_log2,
@@ -353,8 +399,8 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
     __shared__ int hk[256];
     __shared__ int hh[256];    // hubs: neighbours by head rank, then scatter cursors
     __shared__ int hcum[257];  // hubs: neighbours whose list head rank is >= L
-    __shared__ int s_offs[kUnionThreads], s_scan[kUnionThreads / 64];
-    __shared__ long long s_seg[kUnionThreads];
+    __shared__ int s_offs[BS], s_scan[BS / 64];
+    __shared__ long long s_seg[BS];
     __shared__ int s_kmax, s_htop, s_count, s_k, s_size, s_ok, s_os, s_lost, s_head;
     const int tid = threadIdx.x;
     const int bs = blockDim.x;
@@ -373,12 +419,14 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
         // small vertices: thread tid owns arc b + tid for the whole computation;
         // hubs: order the arcs by the head rank of the neighbour's list so that a
         // pass at rank >= L only visits the neighbours whose list reaches rank L
-        const bool small = deg <= kUnionThreads;
+        const bool small = deg <= BS;
         const bool hub = deg > kHubDegree;
         for (int t = tid; t < hcap; t += bs) tab[t] = kEmptyKey;
-        hist[tid] = 0;
-        hk[tid] = 0;
-        hh[tid] = 0;
+        if (tid < 256) {
+            hist[tid] = 0;
+            hk[tid] = 0;
+            hh[tid] = 0;
+        }
         if (tid == 0) {
             s_kmax = 0;
             s_htop = rank[v];
@@ -390,24 +438,38 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
         __syncthreads();
         int kmax_l = 0, htop_l = -1;
         ArcState mine{0, 0, 0};
-        for (int32_t p = b + tid; p < e; p += bs) {
-            const int32_t w = col[p];
-            bytes += 5;
-            if (!small) cursor[p] = 0;
-            if (alive[w]) {
-                const uint32_t mt = prev.meta[w];
+        for (int32_t p0 = b + tid; p0 < e; p0 += bs * kScanUnroll) {
+            int32_t w[kScanUnroll];
+            uint32_t mt[kScanUnroll];
+            bool al[kScanUnroll];
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+                const int32_t p = p0 + u * bs;
+                w[u] = p < e ? col[p] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) al[u] = w[u] >= 0 && alive[w[u]];
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) mt[u] = al[u] ? prev.meta[w[u]] : 0u;
+#pragma unroll
+            for (int u = 0; u < kScanUnroll; ++u) {
+                const int32_t p = p0 + u * bs;
+                if (w[u] < 0) continue;
+                bytes += 5;
+                if (!small) cursor[p] = 0;
+                if (!al[u]) continue;
                 bytes += 4;
-                const int kw = meta_k(mt);
-                const int sz = meta_size(mt);
+                const int kw = meta_k(mt[u]);
+                const int sz = meta_size(mt[u]);
                 atomicAdd(&hk[kw], 1);
                 kmax_l = kw > kmax_l ? kw : kmax_l;
                 if (sz > 0) {
-                    const int hr = meta_head(mt);
+                    const int hr = meta_head(mt[u]);
                     htop_l = hr > htop_l ? hr : htop_l;
                     if (hub) atomicAdd(&hh[hr], 1);
                     if (small) {
                         mine.size = sz;
-                        mine.off = prev.off[w];
+                        mine.off = prev.off[w[u]];
                         bytes += 8;
                     }
                 }
@@ -432,12 +494,19 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
                 }
             }
             __syncthreads();
-            for (int32_t p = b + tid; p < e; p += bs) {
-                const int32_t w = col[p];
-                if (alive[w]) {
-                    const uint32_t mt = prev.meta[w];
-                    if (meta_size(mt) > 0) order[b + atomicAdd(&hh[meta_head(mt)], 1)] = p;
+            for (int32_t p0 = b + tid; p0 < e; p0 += bs * kScanUnroll) {
+                int32_t w[kScanUnroll];
+                uint32_t mt[kScanUnroll];
+#pragma unroll
+                for (int u = 0; u < kScanUnroll; ++u) {
+                    const int32_t p = p0 + u * bs;
+                    w[u] = p < e ? col[p] : -1;
                 }
+#pragma unroll
+                for (int u = 0; u < kScanUnroll; ++u) mt[u] = (w[u] >= 0 && alive[w[u]]) ? prev.meta[w[u]] : 0u;
+#pragma unroll
+                for (int u = 0; u < kScanUnroll; ++u)
+                    if (meta_size(mt[u]) > 0) order[b + atomicAdd(&hh[meta_head(mt[u])], 1)] = p0 + u * bs;
             }
             bytes += tid == 0 ? 9ull * (unsigned long long)deg : 0ull;
             __syncthreads();
@@ -453,9 +522,9 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             if (small) {
                 const int start = mine.cur;
                 const int len = arc_run(prev.keys + mine.off, mine, lo0, bytes);
-                insert_runs(len, mine.off + start, prev, H, M, s_offs, s_seg, s_scan, elems, bytes);
+                insert_runs<BS>(len, mine.off + start, prev, H, M, s_offs, s_seg, s_scan, elems, bytes);
             } else {
-                union_pass_wide(lo0, b, hub ? hcum[lo0] : deg, hub, order, col, alive, prev, cursor, H, M, s_offs,
+                union_pass_wide<BS>(lo0, b, hub ? hcum[lo0] : deg, hub, order, col, alive, prev, cursor, H, M, s_offs,
                                 s_seg, s_scan, elems, bytes);
             }
         }
@@ -465,9 +534,9 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
             if (small) {
                 const int start = mine.cur;
                 const int len = arc_run(prev.keys + mine.off, mine, L, bytes);
-                insert_runs(len, mine.off + start, prev, H, M, s_offs, s_seg, s_scan, elems, bytes);
+                insert_runs<BS>(len, mine.off + start, prev, H, M, s_offs, s_seg, s_scan, elems, bytes);
             } else {
-                union_pass_wide(L, b, hub ? hcum[L] : deg, hub, order, col, alive, prev, cursor, H, M, s_offs,
+                union_pass_wide<BS>(L, b, hub ? hcum[L] : deg, hub, order, col, alive, prev, cursor, H, M, s_offs,
                                 s_seg, s_scan, elems, bytes);
             }
             const int over = s_count > M;
@@ -539,19 +608,28 @@ __global__ __launch_bounds__(256) void k_union(const int32_t* __restrict__ workl
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, int hash_log2,
                   LevelView prev, LevelView cur, int32_t* cursor, int32_t* order, int32_t* changed,
-                  int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer) {
+                  int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer, const int32_t* hubs,
+                  const int* hub_count) {
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
     const size_t lds = sizeof(uint32_t) << hash_log2;
     static size_t lds_set = 65536;
     if (lds > lds_set) {
-        (void)hipFuncSetAttribute((const void*)k_union, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        (void)hipFuncSetAttribute((const void*)k_union<kUnionThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        (void)hipFuncSetAttribute((const void*)k_union<kUnionHubThreads>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         lds_set = lds;
     }
     const bool timed = timer && timer->used < timer->cap;
     if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
-    hipLaunchKernelGGL(k_union, dim3(grid), dim3(kUnionThreads), lds, s, worklist, wl_count, n, rp, col, alive, rank,
-                       M, Mv, hash_log2, prev, cur, cursor, order, changed, changed_count, st);
+    hipLaunchKernelGGL(k_union<kUnionThreads>, dim3(grid), dim3(kUnionThreads), lds, s, worklist, wl_count, n, rp, col,
+                       alive, rank, M, Mv, hash_log2, prev, cur, cursor, order, changed, changed_count, st);
+    // hubs of the worklist: wider blocks for their neighbour walks
+    if (hubs)
+        hipLaunchKernelGGL(k_union<kUnionHubThreads>, dim3(512), dim3(kUnionHubThreads), lds, s, hubs, hub_count, n,
+                           rp, col, alive, rank, M, Mv, hash_log2, prev, cur, cursor, order, changed, changed_count,
+                           st);
     if (timed) {
         (void)hipEventRecord(timer->ev[2 * timer->used + 1], s);
         timer->used += 1;
@@ -624,7 +702,8 @@ void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount
 // member left; or (not cut, m > 0) a member of rank >= k left -- k cannot drop
 // while a neighbour sits at level k; or (not cut, m = 0) always.
 __global__ void k_classify(const int32_t* __restrict__ wl, const int* wl_count, LevelView cur,
-                           int32_t* __restrict__ lostmax, int32_t* __restrict__ rc, int* rc_count) {
+                           int32_t* __restrict__ lostmax, int32_t* __restrict__ rc, int* rc_count,
+                           const int32_t* __restrict__ rp, int32_t* __restrict__ hubs, int* hub_count) {
     const int total = *wl_count;
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x; base < total; base += stride) {
@@ -640,13 +719,17 @@ __global__ void k_classify(const int32_t* __restrict__ wl, const int* wl_count, 
             else if (cur.m[v] > 0) need = L >= k;
             else need = true;
         }
-        const int slot = wave_append_slot(need, rc_count);
-        if (need) rc[slot] = v;
+        const bool hub = need && hubs && rp[v + 1] - rp[v] > kHubDegree;
+        const int slot = wave_append_slot(need && !hub, rc_count);
+        if (need && !hub) rc[slot] = v;
+        const int hs = wave_append_slot(hub, hub_count);
+        if (hub) hubs[hs] = v;
     }
 }
 void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int32_t* lostmax, int32_t* rc,
-                     int* rc_count, hipStream_t s) {
-    hipLaunchKernelGGL(k_classify, dim3(1024), dim3(256), 0, s, wl, wl_count, cur, lostmax, rc, rc_count);
+                     int* rc_count, hipStream_t s, const int32_t* rp, int32_t* hubs, int* hub_count) {
+    hipLaunchKernelGGL(k_classify, dim3(1024), dim3(256), 0, s, wl, wl_count, cur, lostmax, rc, rc_count, rp, hubs,
+                       hub_count);
 }
 
 // ---- Alg. 1: d = |B[v,h] \ {v}| 2^k, and max(d, M 2^(k-1)) when k > 0 ---------------------------
