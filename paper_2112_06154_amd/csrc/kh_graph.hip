@@ -204,6 +204,7 @@ void launch_compact_alive(const uint8_t* alive, int32_t n, int32_t* out, int* co
 __global__ void k_round_reset(RoundState* st, int gate) {
     if (gate && st->stall) return;
     st->min_key = LLONG_MAX;
+    st->min_inexact = LLONG_MAX;
     st->sum_val = 0;
     st->alive_count = 0;
     st->rcount = 0;
@@ -787,10 +788,90 @@ void launch_decide(RoundState* st, int cap, hipStream_t s) {
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(1), 0, s, st, cap);
 }
 
+// Decision of the commit sequence from launch_reduce_hist's sweep: commit when
+// no inexact bound is at or below c' = max(c, min); otherwise stall (the
+// recompute sequence then chooses the sources from a histogram of the bounds).
 __global__ void k_decide_commit(RoundState* st, int cap) {
     if (st->stall) return;
-    decide_round(st, cap);
-    if (st->mode == 1) st->stall = 1;
+    if (st->alive_count == 0) {
+        st->mode = 2;
+        return;
+    }
+    if (st->min_inexact > cur_level(st)) {
+        st->mode = 0;
+        return;
+    }
+    st->mode = 1;
+    st->stall = 1;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_hist(const int64_t* __restrict__ deg,
+                                                     const uint8_t* __restrict__ alive,
+                                                     const uint8_t* __restrict__ exact, int32_t n, RoundState* st) {
+    if (st->stall) return;
+    __shared__ long long smin[4], smi[4];
+    __shared__ int scnt[4];
+    long long mn = LLONG_MAX, mi = LLONG_MAX;
+    int cnt = 0;
+    // four consecutive vertices per thread, all loads issued together
+    const int32_t groups = (n + 3) >> 2;
+    for (int32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += gridDim.x * blockDim.x) {
+        const int32_t v0 = g << 2;
+        uint8_t a[4], x[4];
+        long long k[4];
+        if (v0 + 3 < n) {
+            const uchar4 a4 = reinterpret_cast<const uchar4*>(alive)[g];
+            const uchar4 x4 = reinterpret_cast<const uchar4*>(exact)[g];
+            const longlong2 k01 = reinterpret_cast<const longlong2*>(deg)[2 * g];
+            const longlong2 k23 = reinterpret_cast<const longlong2*>(deg)[2 * g + 1];
+            a[0] = a4.x; a[1] = a4.y; a[2] = a4.z; a[3] = a4.w;
+            x[0] = x4.x; x[1] = x4.y; x[2] = x4.z; x[3] = x4.w;
+            k[0] = k01.x; k[1] = k01.y; k[2] = k23.x; k[3] = k23.y;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool in = v0 + u < n;
+                a[u] = in ? alive[v0 + u] : 0;
+                x[u] = in ? exact[v0 + u] : 1;
+                k[u] = in ? deg[v0 + u] : 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (!a[u]) continue;
+            mn = k[u] < mn ? k[u] : mn;
+            ++cnt;
+            if (!x[u]) mi = k[u] < mi ? k[u] : mi;
+        }
+    }
+    mn = wave_min_ll(mn);
+    mi = wave_min_ll(mi);
+    cnt = wave_sum_i(cnt);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        smin[w] = mn;
+        smi[w] = mi;
+        scnt[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            mn = smin[i] < mn ? smin[i] : mn;
+            mi = smi[i] < mi ? smi[i] : mi;
+            cnt += scnt[i];
+        }
+        if (cnt > 0) {
+            atomicMin(&st->min_key, mn);
+            atomicAdd(&st->alive_count, cnt);
+            if (mi != LLONG_MAX) atomicMin(&st->min_inexact, mi);
+        }
+    }
+}
+void launch_reduce_hist(const int64_t* deg, const uint8_t* alive, const uint8_t* exact, int32_t n, RoundState* st,
+                        hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_reduce_hist, dim3(grid_for((n + 3) / 4, 256, 4096)), dim3(256), 0, s, deg, alive, exact,
+                           n, st);
 }
 void launch_decide_commit(RoundState* st, int cap, hipStream_t s) {
     hipLaunchKernelGGL(k_decide_commit, dim3(1), dim3(1), 0, s, st, cap);

@@ -940,8 +940,7 @@ struct ExactRun {
             s = q;
             for (int r = 0; r < iters_per; ++r) {
                 launch_round_reset(st.p, s, 1);
-                launch_reduce(deg.p, nullptr, alive.p, n, st.p, s, 1);
-                launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, s, nullptr, nullptr, 1);
+                launch_reduce_hist(deg.p, alive.p, exact.p, n, st.p, s);
                 launch_decide_commit(st.p, qbits, s);
                 launch_select_commit(deg.p, alive.p, n, st.p, core.p, rlist.p, mark.p, s);
                 delete_round_masked();
@@ -953,16 +952,17 @@ struct ExactRun {
             }
             s = keep;
         };
-        const int long_iters = 32, short_iters = 4;
+        const int long_iters = 32, short_iters = 2;
         auto record_long = [&](hipStream_t q) { commit_body(q, long_iters); };
         auto record_short = [&](hipStream_t q) { commit_body(q, short_iters); };
         auto record_recompute = [&](hipStream_t q) {
             MsPlanes P = PL.view(PL.qmax);
             P.exact_out = exact.p;
-            if (g->seg) {
-                launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, q, g->seg, shist.p, 0);
-                launch_decide_seg(st.p, g->nseg, shist.p, shi.p, qbits, q);
-            }
+            // the stalled iteration's sweep left c' and an empty histogram: count
+            // the inexact bounds (per graph too in a packed union) and choose
+            launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, q, g->seg, g->seg ? shist.p : nullptr, 0);
+            launch_decide(st.p, qbits, q);
+            if (g->seg) launch_decide_seg(st.p, g->nseg, shist.p, shi.p, qbits, q);
             launch_pick(alive.p, deg.p, exact.p, n, st.p, srcl.p, cap, q, g->seg, PL.gcnt.p, PL.sbit.p, qbits,
                         g->seg ? shi.p : nullptr);
             ms_batch(P, g->items, n, g->rp, g->col, alive.p, adeg.p, srcl.p, 0, &st.p->rc_count, h, deg.p, st.p, q);

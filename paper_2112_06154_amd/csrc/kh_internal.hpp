@@ -60,6 +60,7 @@ struct RoundState {
     int epoch;               // device-side mark epoch (advanced by the round / level resets)
     int fepoch;              // device-side frontier-mark epoch (advanced per mask-BFS hop)
     int overflow;            // an estimate exceeded the representable range
+    long long min_inexact;   // lazy exact peel: smallest bound of an inexact alive vertex
     int stall;               // lazy exact peel: a commit sequence waits for exact recomputations
     int pad_stall;
     unsigned long long te;     // edges traversed (exact h-degree work)
@@ -148,6 +149,10 @@ void launch_decide(RoundState* st, int cap, hipStream_t s);
 // recomputation stalls the sequence (st->stall) instead of picking sources;
 // the gated kernels of the sequence then do nothing until launch_unstall.
 void launch_decide_commit(RoundState* st, int cap, hipStream_t s);
+// One sweep for the commit sequence: min key, alive count and the smallest
+// bound of an inexact vertex.
+void launch_reduce_hist(const int64_t* deg, const uint8_t* alive, const uint8_t* exact, int32_t n, RoundState* st,
+                        hipStream_t s);
 void launch_unstall(RoundState* st, hipStream_t s);
 // Round begin folded into the selection: c = max(c, min key), rounds += 1.
 void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core,
