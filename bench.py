@@ -57,9 +57,56 @@ def measured_traffic(k, stages, hs):
     e = t.get(str(k))
     if not e or e.get("source_sha256_16") != source_hash(k):
         return None
-    if e.get("stage") not in stages or e.get("h") != hs:
+    if e.get("stage") != stages or e.get("h") != hs:
         return None
     return e.get("bytes_per_launch")
+
+
+# the dispatches counted as one launch of a reported kernel (the union's hubs
+# are merged by a second, wider variant inside the same timed launch)
+KERNEL_NAMES = {0: ["k_ms_pull<16>"], 1: ["k_union<256>", "k_union<1024>"]}
+# FETCH_SIZE reads 524,317 KiB for the 1 GiB read by the add kernel of
+# --copy-calib, WRITE_SIZE 1,048,576 KiB for its 1 GiB write
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+
+
+def pmc_summarize(fetch_dir, write_dir, stages, hs):
+    """Per-launch HBM bytes of the two reported kernels from rocprofv3
+    counter_collection.csv files of a FETCH_SIZE run and a WRITE_SIZE run of
+    the same command (KiB per dispatch, scaled by the copy calibration), plus
+    the calibration kernels' readings; written to profiles/traffic_counters.json."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        agg = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for row in csv.DictReader(fh):
+                    if row.get("Counter_Name") != counter:
+                        continue
+                    name = row["Kernel_Name"].split("(")[0].replace("void ", "").replace("kh::", "")
+                    a = agg.setdefault(name, [0, 0.0])
+                    a[0] += 1
+                    a[1] += float(row["Counter_Value"])
+        return agg
+
+    fe, wr = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    out = {"scale": {"FETCH_SIZE": FETCH_SCALE, "WRITE_SIZE": WRITE_SCALE},
+           "calibration": {k: {"fetch_kib": v[1] / v[0]} for k, v in fe.items() if "at::native" in k}}
+    for k, names in KERNEL_NAMES.items():
+        first = names[0]
+        if first not in fe or first not in wr:
+            continue
+        launches = fe[first][0]
+        f_kib = sum(fe[nm][1] for nm in names if nm in fe) / launches
+        w_kib = sum(wr[nm][1] for nm in names if nm in wr) / launches
+        out[str(k)] = {"kernels": names, "source_sha256_16": source_hash(k), "stage": stages, "h": hs,
+                       "launches": launches, "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib,
+                       "bytes_per_launch": int(1024 * (FETCH_SCALE * f_kib + WRITE_SCALE * w_kib))}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
 
 
 def log(*a):
@@ -229,14 +276,15 @@ def bench_serve(kh, ctx, args):
     fin = sorted(done)
     lat = np.array([done[j] for j in fin])
     cls = {}
-    for j in fin:
+    for idx, j in enumerate(fin):
         key = f"{'sampled' if modes[j] else 'exact'}_h{int(hs[j])}"
-        cls.setdefault(key, []).append(lat[j])
+        cls.setdefault(key, []).append(lat[idx])
     return {"requests": nreq, "completed": len(fin), "withdrawn_unserved": cancelled,
             "qps_offered": args.serve_qps, "seconds_offered": args.serve_seconds,
             "wall_s": round(wall, 3), "qps_served": round(len(fin) / wall, 2),
-            "p50_ms": round(1e3 * percentile(lat, 50), 3), "p99_ms": round(1e3 * percentile(lat, 99), 3),
-            "max_ms": round(1e3 * float(lat.max()), 3), "workers": args.serve_workers,
+            "p50_ms": round(1e3 * percentile(lat, 50), 3) if lat.size else None,
+            "p99_ms": round(1e3 * percentile(lat, 99), 3) if lat.size else None,
+            "max_ms": round(1e3 * float(lat.max()), 3) if lat.size else None, "workers": args.serve_workers,
             "pool": {"graphs": len(gs), "max_n": int(cap), "median_n": int(np.median(sizes))},
             "per_class": {k: {"n": len(v), "p50_ms": round(1e3 * percentile(v, 50), 3),
                               "p99_ms": round(1e3 * percentile(v, 99), 3)} for k, v in sorted(cls.items())}}
@@ -325,6 +373,8 @@ def main():
     ap.add_argument("--cl4m-eps", default="0.5,0.25")
     ap.add_argument("--dev-n", type=int, default=100_000)
     ap.add_argument("--skip-main", action="store_true", help="only the --batch / --serve / --cl4m measurements")
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_counters.json from two rocprofv3 --pmc runs of this command")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -337,6 +387,9 @@ def main():
 
     stages = [s for s in args.stages.split(",") if s]
     hs = [int(x) for x in args.hs.split(",")]
+    if args.pmc_summarize:
+        pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], stages, hs)
+        return
     if args.skip_main:
         torch.cuda.set_device(0)
         ctx = kh.Context(0)

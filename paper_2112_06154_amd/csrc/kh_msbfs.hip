@@ -27,6 +27,9 @@
 
 namespace kh {
 
+// Neighbour frontier words a group of the pull kernel gathers at once.
+constexpr int kGatherDepth = 4;
+
 // First visit of a vertex in its 64-vertex tile: the tile joins the visited list.
 __device__ __forceinline__ bool tile_first(int32_t u, uint32_t* __restrict__ bmTile) {
     const int32_t t = u >> 6;
@@ -352,9 +355,9 @@ __global__ __launch_bounds__(256) void k_ms_pull(int32_t nitems, const int32_t* 
                 unsigned long long fm = (__ballot(f) & gmask) >> gbase;
                 if (j == 0) gath += (unsigned long long)__popcll(fm) * 8 * Q;
                 while (fm) {
-                    int32_t ws[4];
+                    int32_t ws[kGatherDepth];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < kGatherDepth; ++u) {
                         ws[u] = -1;
                         if (fm) {
                             const int k = __ffsll((long long)fm) - 1;
@@ -362,10 +365,11 @@ __global__ __launch_bounds__(256) void k_ms_pull(int32_t nitems, const int32_t* 
                             ws[u] = __shfl(w, gbase + k);
                         }
                     }
-                    uint64_t x[4];
+                    uint64_t x[kGatherDepth];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) x[u] = ws[u] >= 0 ? fr_cur[(size_t)ws[u] * Q + j] : 0ull;
-                    a |= x[0] | x[1] | x[2] | x[3];
+                    for (int u = 0; u < kGatherDepth; ++u) x[u] = ws[u] >= 0 ? fr_cur[(size_t)ws[u] * Q + j] : 0ull;
+#pragma unroll
+                    for (int u = 0; u < kGatherDepth; ++u) a |= x[u];
                 }
                 const bool full = ((a | vw) & vm) == vm;
                 if ((__ballot(full) & gmask) == gmask) {
