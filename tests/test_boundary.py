@@ -85,3 +85,19 @@ def test_context_without_gpu_reports_device_error():
         pass
     h = ctypes.c_void_p()
     assert kh.lib().kh_context_create(0, 0, ctypes.byref(h)) == kh.KH_EDEVICE
+
+
+def test_batch_and_serve_reject_missing_arguments():
+    # host-side argument checks; no context or GPU is needed to reach them
+    L = kh.lib()
+    p = kh.make_params(2)
+    res = kh.Result()
+    t = ctypes.c_uint64()
+    assert L.kh_core_batch(None, 1, None, ctypes.byref(p), None, None, None) == -1
+    assert L.kh_core_batch(None, -1, None, ctypes.byref(p), None, None, None) == -1
+    assert L.kh_serve_start(None, 1, 0, 0, 0) == -1
+    assert L.kh_serve_submit(None, None, ctypes.byref(p), None, ctypes.byref(t)) == -1
+    assert L.kh_serve_poll(None, 1, ctypes.byref(res)) == -1
+    assert L.kh_serve_wait(None, 1, ctypes.byref(res)) == -1
+    assert L.kh_serve_cancel(None, 1) == -1
+    assert L.kh_serve_stop(None) == -1
