@@ -65,7 +65,10 @@ struct kh_context {
     std::atomic<uint64_t> used{0};
     size_t lds_per_block = 65536;
     int num_cu = 0;
-    RoundState* host_state = nullptr;  // pinned mirror of the device round state
+    RoundState* host_state = nullptr;  // pinned mirror of the device round state (fallback)
+    // pinned mirrors leased by concurrent calls (StateLease)
+    std::mutex pool_lock;
+    std::vector<RoundState*> pool;
     // pull-kernel timing (kh_profile_enable / kh_profile_read)
     bool prof_on = false;
     PullTimer timer[2];  // 0: h-degree pull, 1: sample-list union
@@ -84,6 +87,41 @@ thread_local bool tl_worker = false;
 
 RoundState* hstate(kh_context* ctx) { return tl_state ? tl_state : ctx->host_state; }
 bool prof_active(const kh_context* ctx) { return ctx->prof_on && !tl_worker; }
+
+// Every entry point that runs an engine leases a pinned round-state mirror of
+// its own for the calling thread, so that calls from several threads on one
+// context never share one (serving threads bring their own).
+struct StateLease {
+    kh_context* ctx = nullptr;
+    RoundState* mine = nullptr;
+    explicit StateLease(kh_context* c) : ctx(c) {
+        if (tl_state) return;
+        {
+            std::lock_guard<std::mutex> lk(ctx->pool_lock);
+            if (!ctx->pool.empty()) {
+                mine = ctx->pool.back();
+                ctx->pool.pop_back();
+            }
+        }
+        if (!mine) {
+            void* q = nullptr;
+            if (hipHostMalloc(&q, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                throw KhError{KH_ENOMEM};
+            }
+            mine = static_cast<RoundState*>(q);
+        }
+        tl_state = mine;
+    }
+    ~StateLease() {
+        if (!mine) return;
+        tl_state = nullptr;
+        std::lock_guard<std::mutex> lk(ctx->pool_lock);
+        ctx->pool.push_back(mine);
+    }
+    StateLease(const StateLease&) = delete;
+    StateLease& operator=(const StateLease&) = delete;
+};
 
 template <typename T>
 struct Buf {
@@ -262,6 +300,7 @@ extern "C" void kh_context_destroy(kh_context* ctx) {
     if (!ctx) return;
     kh::serve_shutdown(ctx);
     if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+    for (RoundState* p : ctx->pool) (void)hipHostFree(p);
     for (auto& T : ctx->timer) {
         if (T.ev) {
             for (int i = 0; i < 2 * T.cap; ++i) (void)hipEventDestroy(T.ev[i]);
@@ -1378,6 +1417,7 @@ extern "C" kh_status kh_core(kh_graph* g, const kh_params* P, int32_t* core_out,
         check_params(g, P);
         if (g->n > 0 && !core_out) fail(KH_EINVAL);
         hip_ok(hipSetDevice(g->ctx->device));
+        StateLease lease(g->ctx);
         auto s = static_cast<hipStream_t>(stream);
         const bool out_dev = (P->flags & KH_OUT_DEVICE) != 0;
         const bool want_dense = (P->flags & KH_WANT_DENSE) != 0;
@@ -1617,6 +1657,7 @@ extern "C" kh_status kh_core_batch(kh_context* ctx, int32_t count, kh_graph* con
         }
         if (P->flags & KH_EARLY_STOP) fail(KH_ENOTIMPL);
         hip_ok(hipSetDevice(ctx->device));
+        StateLease lease(ctx);
         auto s = static_cast<hipStream_t>(stream);
         const bool sampled = P->epsilon > 0.0;
         // chunks of consecutive non-empty graphs: packed ids and arc offsets stay
@@ -1670,6 +1711,7 @@ extern "C" kh_status kh_hdeg(kh_graph* g, int32_t h, const uint8_t* alive_in, ui
         if (g->n > 0 && !deg_out) fail(KH_EINVAL);
         if (g->n == 0) return KH_OK;
         hip_ok(hipSetDevice(g->ctx->device));
+        StateLease lease(g->ctx);
         auto s = static_cast<hipStream_t>(stream);
         kh_context* ctx = g->ctx;
         const int32_t n = g->n;
@@ -1732,6 +1774,7 @@ extern "C" kh_status kh_sampled_lists(kh_graph* g, const kh_params* P, const uin
         if (g->n == 0) return KH_OK;
         if (g->n > kMaxSampledN) fail(KH_ENOTIMPL);
         hip_ok(hipSetDevice(g->ctx->device));
+        StateLease lease(g->ctx);
         auto s = static_cast<hipStream_t>(stream);
         const int32_t n = g->n;
         SampledRun S;
@@ -1786,6 +1829,7 @@ extern "C" kh_status kh_dense(kh_graph* g, const kh_params* P, const int32_t* co
         clear_result(res);
         if (g->n == 0) return KH_OK;
         hip_ok(hipSetDevice(g->ctx->device));
+        StateLease lease(g->ctx);
         auto s = static_cast<hipStream_t>(stream);
         const int32_t n = g->n;
         std::vector<int64_t> hc((size_t)n);

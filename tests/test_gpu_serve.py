@@ -154,3 +154,31 @@ def test_serve_device_outputs(ctx):
             assert np.array_equal(o.cpu().numpy(), kh.core(G, 2)[0])
     finally:
         srv.stop()
+
+
+def test_concurrent_calls_on_one_context(ctx):
+    # plain kh_core calls from several host threads on one context (no server)
+    import threading
+    gs = pool(6, seed=31)
+    Gs = [kh.Graph.from_gg(ctx, g) for g in gs]
+    want = [oracle.exact_core(g, 2) if g.n <= 3000 else kh.core(G, 2)[0].astype(np.int64) for g, G in zip(gs, Gs)]
+    got = [None] * len(gs)
+    errors = []
+
+    def run(i):
+        try:
+            for _ in range(3):
+                c, _ = kh.core(Gs[i], 2)
+                got[i] = c.astype(np.int64)
+        except Exception as e:  # noqa: BLE001
+            errors.append(e)
+
+    say("concurrent kh_core threads")
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(len(gs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors
+    for g, w, c in zip(gs, want, got):
+        assert np.array_equal(c, w), g.name
