@@ -994,28 +994,59 @@ struct ExactRun {
         const int long_iters = 32, short_iters = 2;
         auto record_long = [&](hipStream_t q) { commit_body(q, long_iters); };
         auto record_short = [&](hipStream_t q) { commit_body(q, short_iters); };
-        auto record_recompute = [&](hipStream_t q) {
-            MsPlanes P = PL.view(PL.qmax);
-            P.exact_out = exact.p;
-            // the stalled iteration's sweep left c' and an empty histogram: count
-            // the inexact bounds (per graph too in a packed union) and choose
+        // Recomputation: count the inexact bounds left by the stalled sweep
+        // (per graph too in a packed union), choose and pick the sources.
+        auto record_pick = [&](hipStream_t q) {
             launch_bound_hist(alive.p, deg.p, exact.p, n, st.p, q, g->seg, g->seg ? shist.p : nullptr, 0);
             launch_decide(st.p, qbits, q);
             if (g->seg) launch_decide_seg(st.p, g->nseg, shist.p, shi.p, qbits, q);
             launch_pick(alive.p, deg.p, exact.p, n, st.p, srcl.p, cap, q, g->seg, PL.gcnt.p, PL.sbit.p, qbits,
                         g->seg ? shi.p : nullptr);
+        };
+        // then the bit-parallel BFS of the picked sources with Q words per
+        // vertex, and lift the stall
+        auto record_bfs = [&](hipStream_t q, int qq) {
+            MsPlanes P = PL.view(qq);
+            P.exact_out = exact.p;
             ms_batch(P, g->items, n, g->rp, g->col, alive.p, adeg.p, srcl.p, 0, &st.p->rc_count, h, deg.p, st.p, q);
             launch_unstall(st.p, q);
+        };
+        auto record_recompute = [&](hipStream_t q) {
+            record_pick(q);
+            record_bfs(q, PL.qmax);
         };
         const bool use_graph = !graphs_off() && !prof_active(ctx);
         PL.timer = prof_active(ctx) ? &ctx->timer[0] : nullptr;
         const hipStream_t q = rp.prepare(caller, use_graph, record_long);
         const int i_short = rp.add(record_short);
-        const int i_rec = rp.add(record_recompute);
+        // One graph: the host reads how many sources were picked and replays the
+        // BFS captured for the narrowest bit planes that hold them (a batch of
+        // 40 sources does not need 16 words per vertex).  A packed union keeps
+        // the full width: its sources carry per-graph bit positions.
+        const bool adaptive = g->seg == nullptr;
+        int i_rec = -1, i_pick = -1;
+        std::vector<int> i_bfs(5, -1);
+        if (adaptive) {
+            i_pick = rp.add(record_pick);
+            for (int lq = 0; (1 << lq) <= PL.qmax; ++lq)
+                i_bfs[(size_t)lq] = rp.add([&, lq](hipStream_t qs) { record_bfs(qs, 1 << lq); });
+        } else {
+            i_rec = rp.add(record_recompute);
+        }
         bool stalled = false;
         for (;;) {
             if (stalled) {
-                rp.run(record_recompute, i_rec);
+                if (adaptive) {
+                    rp.run(record_pick, i_pick);
+                    read_state(ctx, st.p, q);
+                    const int picked = std::min(hstate(ctx)->rc_count, qbits);
+                    const int qq = std::min(PL.qmax, pick_q(std::max(picked, 1)));
+                    int lq = 0;
+                    while ((1 << lq) < qq) ++lq;
+                    rp.run([&](hipStream_t qs) { record_bfs(qs, qq); }, i_bfs[(size_t)lq]);
+                } else {
+                    rp.run(record_recompute, i_rec);
+                }
                 rp.run(record_short, i_short);
                 iters += short_iters + 1;
             } else {
