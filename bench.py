@@ -64,7 +64,8 @@ def measured_traffic(k, stages, hs):
 
 # the dispatches counted as one launch of a reported kernel (the union's hubs
 # are merged by a second, wider variant inside the same timed launch)
-KERNEL_NAMES = {0: ["k_ms_pull<16>"], 1: ["k_union<256>", "k_union<1024>"]}
+KERNEL_NAMES = {0: ["k_ms_pull<16>", "k_ms_pull<8>", "k_ms_pull<4>", "k_ms_pull<2>", "k_ms_pull<1>"],
+                1: ["k_union<256>", "k_union<1024>"]}
 # FETCH_SIZE reads 524,317 KiB for the 1 GiB read by the add kernel of
 # --copy-calib, WRITE_SIZE 1,048,576 KiB for its 1 GiB write
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
@@ -98,7 +99,9 @@ def pmc_summarize(fetch_dir, write_dir, stages, hs):
         first = names[0]
         if first not in fe or first not in wr:
             continue
-        launches = fe[first][0]
+        # one timed launch = one dispatch of the first variant (the union), or
+        # of any variant (the pull kernel's widths)
+        launches = sum(fe[nm][0] for nm in names if nm in fe) if k == 0 else fe[first][0]
         f_kib = sum(fe[nm][1] for nm in names if nm in fe) / launches
         w_kib = sum(wr[nm][1] for nm in names if nm in wr) / launches
         out[str(k)] = {"kernels": names, "source_sha256_16": source_hash(k), "stage": stages, "h": hs,
@@ -356,6 +359,8 @@ def main():
     ap.add_argument("--hs", default="2")
     ap.add_argument("--cpu-budget", type=float, default=8.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-te", action="store_true",
+                    help="skip the untimed edges-traversed pass (counter runs: only timed-region dispatches)")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--batch", action="store_true", help="also measure the batch workload (kh_core_batch)")
     ap.add_argument("--batch-count", type=int, default=4096)
@@ -424,7 +429,7 @@ def main():
     # edges traversed of one all-vertex h-degree pass, per h (outside the timed region)
     te_pass = {}
     for h in hs:
-        _, te_pass[h] = kh.hdeg(G, h, out=out)
+        te_pass[h] = 0 if args.no_te else kh.hdeg(G, h, out=out)[1]
     torch.cuda.synchronize()
 
     def step(record):

@@ -1243,9 +1243,13 @@ struct SampledRun {
         const int32_t n = g->n;
         launch_union1(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.view(1), nullptr, nullptr, st.p,
                       s);
-        for (int i = 2; i <= h; ++i)
+        kh_context* ctx = g->ctx;
+        PullTimer* utimer = prof_active(ctx) ? &ctx->timer[1] : nullptr;
+        for (int i = 2; i <= h; ++i) {
+            if (utimer && utimer->used + 2 >= utimer->cap) prof_collect(ctx);
             launch_union(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.hash_log2, L.view(i - 1),
-                         L.view(i), cursor.p, order.p, nullptr, nullptr, st.p, s);
+                         L.view(i), cursor.p, order.p, nullptr, nullptr, st.p, s, utimer);
+        }
         launch_estimate(nullptr, nullptr, n, alive.p, rank.p, L.size[h].p, L.kk[h].p, M, Mv, d.p, st.p, s);
     }
 
