@@ -305,11 +305,12 @@ def bench_cl4m(kh, ctx, args):
     import graphgen as gg
     out = {}
     t0 = time.time()
-    g = gg.workload("cl4m")
-    log(f"cl4m generated in {time.time() - t0:.1f}s")
+    g = gg.workload("cl4m") if not args.dev_only else gg.empty(1)
+    if not args.dev_only:
+        log(f"cl4m generated in {time.time() - t0:.1f}s")
     G = kh.Graph.from_gg(ctx, g)
     core_out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
-    for eps in [float(x) for x in args.cl4m_eps.split(",")]:
+    for eps in ([] if args.dev_only else [float(x) for x in args.cl4m_eps.split(",")]):
         torch.cuda.synchronize()
         t = time.perf_counter()
         _, res = kh.core(G, 3, epsilon=eps, delta=0.05, seed=1, out=core_out, dense=True, prune=True)
@@ -377,6 +378,7 @@ def main():
     ap.add_argument("--cl4m", action="store_true", help="also measure the 4M-vertex sampled workload")
     ap.add_argument("--cl4m-eps", default="0.5,0.25")
     ap.add_argument("--dev-n", type=int, default=100_000)
+    ap.add_argument("--dev-only", action="store_true", help="--cl4m: only the deviation study")
     ap.add_argument("--skip-main", action="store_true", help="only the --batch / --serve / --cl4m measurements")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_counters.json from two rocprofv3 --pmc runs of this command")
