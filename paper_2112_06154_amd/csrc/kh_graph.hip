@@ -143,14 +143,8 @@ __global__ void k_fill(T* __restrict__ p, T v, int64_t count) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
-void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s) {
-    if (count > 0) hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, v, count);
-}
 void launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s) {
     if (count > 0) hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, v, count);
-}
-void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s) {
-    if (count > 0) hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, v, count);
 }
 void launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t s) {
     if (count > 0) hipLaunchKernelGGL(k_fill<int64_t>, dim3(grid_for(count, 256, 8192)), dim3(256), 0, s, p, v, count);
@@ -595,92 +589,13 @@ void launch_lower_bound(const int32_t* list, const int* count, int32_t n, int h,
                        exact);
 }
 
-__global__ void k_lazy_candidates(const uint8_t* __restrict__ alive, const int64_t* __restrict__ deg,
-                                  const uint8_t* __restrict__ exact, int32_t n, RoundState* st,
-                                  int32_t* __restrict__ out, int pass, int opt_cap) {
-    if (st->alive_count == 0) return;
-    const long long c = st->min_key > st->c ? st->min_key : st->c;
-    const long long hi = c + c / 8 + 32;
-    const int base_fill = pass ? st->rc_count : 0;
-    const int room = opt_cap - base_fill;
-    if (pass && room <= 0) return;
-    const int32_t stride = gridDim.x * blockDim.x;
-    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const int32_t v = base + threadIdx.x;
-        bool want = false;
-        if (v < n && alive[v] && !exact[v]) {
-            const long long d = deg[v];
-            want = pass ? (d > c && d <= hi) : (d <= c);
-        }
-        if (!pass) {
-            const int slot = wave_append_slot(want, &st->rc_count);
-            if (want) out[slot] = v;
-        } else {
-            if (*(volatile int*)&st->opt_count >= room) continue;
-            const int slot = wave_append_slot(want, &st->opt_count);
-            if (want && slot < room) out[base_fill + slot] = v;
-        }
-    }
-}
-void launch_lazy_candidates(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
-                            int32_t* out, int pass, int opt_cap, hipStream_t s) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_lazy_candidates, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, alive, deg, exact, n, st,
-                           out, pass, opt_cap);
-}
 
-// Deleting R can only remove from N(v;h,X) vertices within distance h - t of R,
-// t = dist(v, R): a shortest path from v that needed R reaches some r in R after
-// at least t steps and has at most h - t left.  So
-//     deg_h(v; X \ R) >= deg_h(v; X) - |N(R; h - t, X)|,
-// and |N(R; s, X)| = |R| + (vertices the BFS from R found in hops 1..s).
-__global__ void k_decay_bound(const int32_t* __restrict__ alist, RoundState* st, const int* __restrict__ hopfill,
-                              int h, const uint8_t* __restrict__ alive, const int32_t* __restrict__ adeg,
-                              const int32_t* __restrict__ anchor, int64_t* __restrict__ deg,
-                              uint8_t* __restrict__ exact) {
-    const int total = st->aff_fill;
-    const long long rc = st->rcount;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        const int32_t v = alist[i];
-        if (!alive[v]) continue;
-        if (h == 1) {
-            deg[v] = adeg[v];
-            exact[v] = 1;
-            continue;
-        }
-        int t = 1;
-        while (t < h && i >= hopfill[t]) ++t;
-        const long long lost = rc + (h - t >= 1 ? (long long)hopfill[h - t] : 0ll);
-        long long lb = deg[v] - lost;
-        long long ab = adeg[v];
-        int32_t x = v;
-        for (int q = 1; q < h; ++q) {
-            x = anchor[x];
-            if (x < 0 || !alive[x]) break;
-            const long long a = adeg[x];
-            ab = a > ab ? a : ab;
-        }
-        deg[v] = lb > ab ? lb : ab;
-        exact[v] = 0;
-    }
-}
-void launch_decay_bound(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
-                        const int32_t* adeg, const int32_t* anchor, int64_t* deg, uint8_t* exact, hipStream_t s) {
-    hipLaunchKernelGGL(k_decay_bound, dim3(1024), dim3(256), 0, s, alist, st, hopfill, h, alive, adeg, anchor, deg,
-                       exact);
-}
 
 __global__ void k_record_fill(RoundState* st, int* hopfill, int t) { hopfill[t] = st->aff_fill; }
 void launch_record_fill(RoundState* st, int* hopfill, int t, hipStream_t s) {
     hipLaunchKernelGGL(k_record_fill, dim3(1), dim3(1), 0, s, st, hopfill, t);
 }
 
-__global__ void k_set_flags(const int32_t* __restrict__ list, int count, uint8_t* __restrict__ flags, uint8_t v) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) flags[list[i]] = v;
-}
-void launch_set_flags(const int32_t* list, int count, uint8_t* flags, uint8_t v, hipStream_t s) {
-    if (count > 0) hipLaunchKernelGGL(k_set_flags, dim3(grid_for(count, 256, 4096)), dim3(256), 0, s, list, count, flags, v);
-}
 
 // ---- device-driven rounds of the lazy exact peel -------------------------------------------
 __device__ __forceinline__ long long cur_level(const RoundState* st) {
@@ -916,48 +831,8 @@ void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact,
     hipLaunchKernelGGL(k_pick_finish, dim3(1), dim3(1), 0, s, st, cap);
 }
 
-__global__ void k_mark_exact(const int32_t* __restrict__ list, RoundState* st, uint8_t* __restrict__ exact) {
-    const int cnt = st->ms_ns;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) exact[list[i]] = 1;
-}
-void launch_mark_exact(const int32_t* list, RoundState* st, uint8_t* exact, hipStream_t s) {
-    hipLaunchKernelGGL(k_mark_exact, dim3(4), dim3(256), 0, s, list, st, exact);
-}
 
-__global__ void k_round_begin_gated(RoundState* st) {
-    if (st->mode != 0) return;
-    const long long c = cur_level(st);
-    st->c = c;
-    st->rounds += 1;
-}
-void launch_round_begin_gated(RoundState* st, hipStream_t s) {
-    hipLaunchKernelGGL(k_round_begin_gated, dim3(1), dim3(1), 0, s, st);
-}
 
-__global__ void k_select_gated(const int64_t* __restrict__ key, uint8_t* __restrict__ alive, int32_t n, RoundState* st,
-                               int64_t* __restrict__ core, int32_t* __restrict__ rlist, int32_t* __restrict__ mark,
-                               int32_t epoch) {
-    if (st->mode != 0) return;
-    if (epoch < 0) epoch = st->epoch;
-    const long long c = st->c;
-    const int32_t stride = gridDim.x * blockDim.x;
-    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const int32_t v = base + threadIdx.x;
-        const bool take = v < n && alive[v] && key[v] <= c;
-        const int slot = wave_append_slot(take, &st->rcount);
-        if (take) {
-            core[v] = c;
-            rlist[slot] = v;
-            mark[v] = epoch;
-        }
-    }
-}
-void launch_select_gated(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core, int32_t* rlist,
-                         int32_t* mark, int32_t epoch, hipStream_t s) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_select_gated, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, key, alive, n, st, core,
-                           rlist, mark, epoch);
-}
 
 __global__ void k_select_commit(const int64_t* __restrict__ key, uint8_t* __restrict__ alive, int32_t n,
                                 RoundState* st, int64_t* __restrict__ core, int32_t* __restrict__ rlist,
@@ -1014,14 +889,6 @@ void launch_rbfs_init(const int32_t* rlist, RoundState* st, uint64_t* rmask, uin
     hipLaunchKernelGGL(k_rbfs_init, dim3(64), dim3(256), 0, s, rlist, st, rmask, gain);
 }
 
-__global__ void k_rbfs_hop_reset(RoundState* st, int t) {
-    st->fepoch += 1;
-    st->qcount = 0;
-    st->fcount[t & 1] = 0;
-}
-void launch_rbfs_hop_reset(RoundState* st, int t, hipStream_t s) {
-    hipLaunchKernelGGL(k_rbfs_hop_reset, dim3(1), dim3(1), 0, s, st, t);
-}
 
 __global__ void k_rbfs_expand(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
                               const int32_t* __restrict__ rp, const int32_t* __restrict__ col,

@@ -92,9 +92,7 @@ void launch_pack_col(int32_t count, const int64_t* a_off, const int32_t* v_off, 
 void launch_unpack_i32(int32_t count, const int32_t* v_off, const uint64_t* dst_ptrs, int32_t total,
                        const int32_t* src, hipStream_t s);
 void launch_validate(const int32_t* rp, const int32_t* col, int32_t n, int64_t nnz, int* err, hipStream_t s);
-void launch_fill_u8(uint8_t* p, uint8_t v, int64_t count, hipStream_t s);
 void launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t s);
-void launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t s);
 void launch_fill_i64(int64_t* p, int64_t v, int64_t count, hipStream_t s);
 void launch_alive_from(const uint8_t* src, uint8_t* alive, int32_t n, hipStream_t s);
 void launch_alive_degree(const int32_t* rp, const int32_t* col, const uint8_t* alive, int32_t* adeg, int32_t n,
@@ -130,17 +128,7 @@ void launch_anchor(const int32_t* list, const int* count, int32_t n, const int32
 // deg[v] = a lower bound of deg_h(v;X) (alive degrees along the anchor chain), exact[v] = (h == 1).
 void launch_lower_bound(const int32_t* list, const int* count, int32_t n, int h, const uint8_t* alive,
                         const int32_t* adeg, const int32_t* anchor, int64_t* deg, uint8_t* exact, hipStream_t s);
-// After deleting R: for the affected vertex alist[i] found at BFS hop t,
-// deg <- max(deg - |N(R; h-t)|, anchor bound), exact = (h == 1).  hopfill[t] = affected
-// vertices found in hops 1..t.
-void launch_decay_bound(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
-                        const int32_t* adeg, const int32_t* anchor, int64_t* deg, uint8_t* exact, hipStream_t s);
 void launch_record_fill(RoundState* st, int* hopfill, int t, hipStream_t s);
-// pass 0: out[0..rc_count) = {alive v : !exact[v], deg[v] <= c'}, c' = max(c, min key);
-// pass 1: out[rc_count + i] for i < opt_cap - rc_count: inexact v with c' < deg[v] <= c' + c'/8 + 32.
-void launch_lazy_candidates(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
-                            int32_t* out, int pass, int opt_cap, hipStream_t s);
-void launch_set_flags(const int32_t* list, int count, uint8_t* flags, uint8_t v, hipStream_t s);
 // device-driven exact peel steps
 void launch_bound_hist(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
                        hipStream_t s, const int32_t* seg = nullptr, int* shist = nullptr, int gate = 0);
@@ -173,12 +161,9 @@ void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact,
                  int32_t* sbit = nullptr, int qbits = 0, const long long* shi = nullptr);
 // Per-segment thresholds shi[seg] (packed unions) from per-segment histograms.
 void launch_decide_seg(RoundState* st, int nseg, int* shist, long long* shi, int cap, hipStream_t s);
-void launch_mark_exact(const int32_t* list, RoundState* st, uint8_t* exact, hipStream_t s);
-void launch_round_begin_gated(RoundState* st, hipStream_t s);
 // R-mask BFS: after h hops rmask[v] holds bit (j mod 64) for every deleted r_j within
 // distance h of v in G[X]; first-visited vertices are appended to alist in hop order.
 void launch_rbfs_init(const int32_t* rlist, RoundState* st, uint64_t* rmask, uint64_t* gain, hipStream_t s);
-void launch_rbfs_hop_reset(RoundState* st, int t, hipStream_t s);
 void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
                         const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
                         int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
@@ -188,8 +173,6 @@ void launch_clear_u64_list(const int32_t* list, const int* count, uint64_t* arr,
 void launch_decay_masked(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
                          const int32_t* adeg, const int32_t* anchor, const uint64_t* rmask, int64_t* deg,
                          uint8_t* exact, hipStream_t s);
-void launch_select_gated(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core, int32_t* rlist,
-                         int32_t* mark, int32_t epoch, hipStream_t s);
 
 // ---- kernels: bit-parallel multi-source bounded BFS (kh_msbfs.hip) ---------------------
 
