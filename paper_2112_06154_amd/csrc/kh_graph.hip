@@ -195,8 +195,7 @@ void launch_compact_alive(const uint8_t* alive, int32_t n, int32_t* out, int* co
 }
 
 // ---- round bookkeeping ------------------------------------------------------------------
-__global__ void k_round_reset(RoundState* st, int gate) {
-    if (gate && st->stall) return;
+__device__ void round_reset_fields(RoundState* st) {
     st->min_key = LLONG_MAX;
     st->min_inexact = LLONG_MAX;
     st->sum_val = 0;
@@ -211,12 +210,16 @@ __global__ void k_round_reset(RoundState* st, int gate) {
     st->changed_count[0] = 0;
     st->changed_count[1] = 0;
     st->rc_count = 0;
-    st->opt_count = 0;
     st->ms_ns = 0;
     for (int b = 0; b < 48; ++b) st->hist[b] = 0;
     st->fcount[0] = 0;
     st->fcount[1] = 0;
     st->epoch += 1;
+    st->fepoch += 1;  // frontier marks of the mask BFS's first hop
+}
+__global__ void k_round_reset(RoundState* st, int gate) {
+    if (gate && st->stall) return;
+    round_reset_fields(st);
 }
 void launch_round_reset(RoundState* st, hipStream_t s, int gate) {
     hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(1), 0, s, st, gate);
@@ -360,6 +363,44 @@ __global__ void k_enqueue(const int32_t* __restrict__ list, const int* lo_p, con
 void launch_enqueue(const int32_t* list, const int* lo, const int* hi, const int32_t* rp, int32_t* qv, int32_t* qb,
                     int* qcount, hipStream_t s) {
     hipLaunchKernelGGL(k_enqueue, dim3(512), dim3(256), 0, s, list, lo, hi, rp, qv, qb, qcount);
+}
+
+__global__ void k_enqueue_r(const int32_t* __restrict__ rlist, const int* rcount, const int32_t* __restrict__ rp,
+                            int32_t* __restrict__ qv, int32_t* __restrict__ qb, int* qcount, int mode,
+                            uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain, uint8_t* __restrict__ alive) {
+    const int hi = *rcount;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < hi; base += stride) {
+        const int i = base + threadIdx.x;
+        int v = 0, nch = 0;
+        if (i < hi) {
+            v = rlist[i];
+            if (mode == 0) {
+                const unsigned long long b = 1ull << (i & 63);
+                atomicOr((unsigned long long*)&rmask[v], b);
+                atomicOr((unsigned long long*)&gain[v], b);
+            } else {
+                alive[v] = 0;
+            }
+            const int d = rp[v + 1] - rp[v];
+            nch = (d + kExpandChunk - 1) / kExpandChunk;
+        }
+        const int incl = wave_incl_scan(nch);
+        const int total = __shfl(incl, 63);
+        int wbase = 0;
+        if (lane_id() == 63 && total > 0) wbase = atomicAdd(qcount, total);
+        wbase = __shfl(wbase, 63);
+        const int first = wbase + incl - nch;
+        for (int c = 0; c < nch; ++c) {
+            qv[first + c] = v;
+            qb[first + c] = rp[v] + c * kExpandChunk;
+        }
+    }
+}
+void launch_enqueue_r(const int32_t* rlist, const int* rcount, const int32_t* rp, int32_t* qv, int32_t* qb, int* qcount,
+                      int mode, uint64_t* rmask, uint64_t* gain, uint8_t* alive, hipStream_t s) {
+    hipLaunchKernelGGL(k_enqueue_r, dim3(256), dim3(256), 0, s, rlist, rcount, rp, qv, qb, qcount, mode, rmask, gain,
+                       alive);
 }
 
 __global__ void k_expand(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
@@ -703,23 +744,6 @@ void launch_decide(RoundState* st, int cap, hipStream_t s) {
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(1), 0, s, st, cap);
 }
 
-// Decision of the commit sequence from launch_reduce_hist's sweep: commit when
-// no inexact bound is at or below c' = max(c, min); otherwise stall (the
-// recompute sequence then chooses the sources from a histogram of the bounds).
-__global__ void k_decide_commit(RoundState* st, int cap) {
-    if (st->stall) return;
-    if (st->alive_count == 0) {
-        st->mode = 2;
-        return;
-    }
-    if (st->min_inexact > cur_level(st)) {
-        st->mode = 0;
-        return;
-    }
-    st->mode = 1;
-    st->stall = 1;
-}
-
 __global__ __launch_bounds__(256) void k_reduce_hist(const int64_t* __restrict__ deg,
                                                      const uint8_t* __restrict__ alive,
                                                      const uint8_t* __restrict__ exact, int32_t n, RoundState* st) {
@@ -788,10 +812,10 @@ void launch_reduce_hist(const int64_t* deg, const uint8_t* alive, const uint8_t*
         hipLaunchKernelGGL(k_reduce_hist, dim3(grid_for((n + 3) / 4, 256, 4096)), dim3(256), 0, s, deg, alive, exact,
                            n, st);
 }
-void launch_decide_commit(RoundState* st, int cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_decide_commit, dim3(1), dim3(1), 0, s, st, cap);
+__global__ void k_unstall(RoundState* st) {
+    st->stall = 0;
+    round_reset_fields(st);
 }
-__global__ void k_unstall(RoundState* st) { st->stall = 0; }
 void launch_unstall(RoundState* st, hipStream_t s) { hipLaunchKernelGGL(k_unstall, dim3(1), dim3(1), 0, s, st); }
 
 __global__ void k_pick(const uint8_t* __restrict__ alive, const int64_t* __restrict__ deg,
@@ -837,14 +861,20 @@ void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact,
 __global__ void k_select_commit(const int64_t* __restrict__ key, uint8_t* __restrict__ alive, int32_t n,
                                 RoundState* st, int64_t* __restrict__ core, int32_t* __restrict__ rlist,
                                 int32_t* __restrict__ mark) {
-    if (st->mode != 0 || st->stall) return;
-    const int32_t epoch = st->epoch;
-    // every block computes the same level; block 0 records it
+    if (st->stall) return;
+    // every block takes the same decision from the sweep's reductions; block 0 records it
     const long long c = cur_level(st);
+    const int mode = st->alive_count == 0 ? 2 : (st->min_inexact > c ? 0 : 1);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->c = c;
-        st->rounds += 1;
+        st->mode = mode;
+        if (mode == 1) st->stall = 1;
+        if (mode == 0) {
+            st->c = c;
+            st->rounds += 1;
+        }
     }
+    if (mode != 0) return;
+    const int32_t epoch = st->epoch;
     const int32_t stride = gridDim.x * blockDim.x;
     for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
         const int32_t v = base + threadIdx.x;
@@ -868,28 +898,8 @@ void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundSt
 // For v at distance exactly h from R, every vertex that leaves N(v;h,X) when R is
 // deleted is itself in R (a path that needed R reaches it after h steps), so
 // deg_h(v; X \ R) = deg_h(v; X) - |R ∩ N(v;h,X)|: an exact update.  The mask BFS
-// gives |R ∩ N(v;h,X)| as a popcount when |R| <= 64.
-__global__ void k_rbfs_init(const int32_t* __restrict__ rlist, RoundState* st, uint64_t* __restrict__ rmask,
-                            uint64_t* __restrict__ gain) {
-    const int cnt = st->rcount;
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < cnt; j += gridDim.x * blockDim.x) {
-        const int32_t r = rlist[j];
-        const unsigned long long b = 1ull << (j & 63);
-        atomicOr((unsigned long long*)&rmask[r], b);
-        atomicOr((unsigned long long*)&gain[r], b);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // resets of hop 1 (no thread of this kernel reads them)
-        st->fepoch += 1;
-        st->qcount = 0;
-        st->fcount[1] = 0;
-    }
-}
-void launch_rbfs_init(const int32_t* rlist, RoundState* st, uint64_t* rmask, uint64_t* gain, hipStream_t s) {
-    hipLaunchKernelGGL(k_rbfs_init, dim3(64), dim3(256), 0, s, rlist, st, rmask, gain);
-}
-
-
+// gives |R ∩ N(v;h,X)| as a popcount when |R| <= 64 (R's bits are set by
+// launch_enqueue_r).
 __global__ void k_rbfs_expand(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
                               const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                               const uint8_t* __restrict__ alive, const uint64_t* __restrict__ gain_cur,
@@ -955,16 +965,31 @@ void launch_hop_end(RoundState* st, int* hopfill, int t, int h, hipStream_t s) {
 
 __global__ void k_clear_u64_lists3(const int32_t* __restrict__ l0, const int* c0, uint64_t* __restrict__ a0,
                                    const int32_t* __restrict__ l1, const int* c1, uint64_t* __restrict__ a1,
-                                   const int32_t* __restrict__ l2, const int* c2, uint64_t* __restrict__ a2) {
+                                   const int32_t* __restrict__ l2, const int* c2, uint64_t* __restrict__ a2,
+                                   RoundState* st) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
     const int n0 = *c0, n1 = *c1, n2 = *c2;
     for (int i = tid; i < n0; i += nth) a0[l0[i]] = 0ull;
     for (int i = tid; i < n1; i += nth) a1[l1[i]] = 0ull;
     for (int i = tid; i < n2; i += nth) a2[l2[i]] = 0ull;
+    if (!st) return;
+    // the last block to finish resets the round state for the next round:
+    // every block has consumed the counts it read before it is counted, and
+    // the reset touches nothing the blocks write, so no fence is needed (a
+    // device-scope fence per block would write back L2 on every XCD)
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&st->blocks_done, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        st->blocks_done = 0;
+        if (!st->stall) round_reset_fields(st);
+    }
 }
 void launch_clear_u64_lists3(const int32_t* l0, const int* c0, uint64_t* a0, const int32_t* l1, const int* c1,
-                             uint64_t* a1, const int32_t* l2, const int* c2, uint64_t* a2, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_u64_lists3, dim3(512), dim3(256), 0, s, l0, c0, a0, l1, c1, a1, l2, c2, a2);
+                             uint64_t* a1, const int32_t* l2, const int* c2, uint64_t* a2, hipStream_t s,
+                             RoundState* st) {
+    hipLaunchKernelGGL(k_clear_u64_lists3, dim3(512), dim3(256), 0, s, l0, c0, a0, l1, c1, a1, l2, c2, a2, st);
 }
 
 __global__ void k_clear_u64_list(const int32_t* __restrict__ list, const int* count, uint64_t* __restrict__ arr) {

@@ -897,21 +897,23 @@ struct ExactRun {
     // alive degrees drop.  Every list count it reads is zero when no round was
     // committed.
     void delete_round_masked() {
-        launch_rbfs_init(rlist.p, st.p, rmask.p, gainA.p, s);
+        // R's mask bits and the chunks of hop 1 (the round reset zeroed qcount)
+        launch_enqueue_r(rlist.p, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, 0, rmask.p, gainA.p, nullptr, s);
         int32_t* fl[2] = {flA.p, flB.p};
         uint64_t* gain[2] = {gainA.p, gainB.p};
         for (int t = 1; t <= h; ++t) {
             const int32_t* src = t == 1 ? rlist.p : fl[(t - 1) & 1];
             const int* srcn = t == 1 ? &st.p->rcount : &st.p->fcount[(t - 1) & 1];
-            launch_enqueue(src, nullptr, srcn, g->rp, qv.p, qb.p, &st.p->qcount, s);
+            if (t > 1) launch_enqueue(src, nullptr, srcn, g->rp, qv.p, qb.p, &st.p->qcount, s);
             launch_rbfs_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, gain[(t - 1) & 1], rmask.p,
                                gain[t & 1], mark.p, -1, fmark.p, -1, fl[t & 1], &st.p->fcount[t & 1], alist.p,
                                &st.p->aff_fill, st.p, s);
             launch_clear_u64_list(src, srcn, gain[(t - 1) & 1], s);
             launch_hop_end(st.p, hopfill.p, t, h, s);
         }
-        launch_kill_list(rlist.p, &st.p->rcount, alive.p, s);
-        launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, s);
+        // R leaves X and its chunks are queued (hop_end of hop h zeroed qcount);
+        // the alive degrees drop
+        launch_enqueue_r(rlist.p, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, 1, nullptr, nullptr, alive.p, s);
         launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, 0, 1, nullptr, nullptr, adeg.p, s);
     }
 
@@ -952,6 +954,7 @@ struct ExactRun {
         launch_fill_i64(core.p, -1, n, s);
         launch_anchor(nullptr, nullptr, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 0, s);
         launch_lower_bound(nullptr, nullptr, n, h, alive.p, adeg.p, anchor.p, deg.p, exact.p, s);
+        launch_round_reset(st.p, s, 0);
         long long iters = 0;
         // one batch takes up to 64 Q sources, per graph of a packed union
         const int qbits = 64 * PL.qmax;
@@ -977,17 +980,17 @@ struct ExactRun {
         auto commit_body = [&](hipStream_t q, int iters_per) {
             const hipStream_t keep = s;
             s = q;
+            // the round state is reset by the previous round's last kernel (or
+            // by the recompute sequence, or before the first replay)
             for (int r = 0; r < iters_per; ++r) {
-                launch_round_reset(st.p, s, 1);
                 launch_reduce_hist(deg.p, alive.p, exact.p, n, st.p, s);
-                launch_decide_commit(st.p, qbits, s);
                 launch_select_commit(deg.p, alive.p, n, st.p, core.p, rlist.p, mark.p, s);
                 delete_round_masked();
                 launch_anchor(alist.p, &st.p->aff_fill, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 1, s);
                 launch_decay_masked(alist.p, st.p, hopfill.p, h, alive.p, adeg.p, anchor.p, rmask.p, deg.p, exact.p,
                                     s);
                 launch_clear_u64_lists3(fl[h & 1], &st.p->fcount[h & 1], gain[h & 1], alist.p, &st.p->aff_fill,
-                                        rmask.p, rlist.p, &st.p->rcount, rmask.p, s);
+                                        rmask.p, rlist.p, &st.p->rcount, rmask.p, s, st.p);
             }
             s = keep;
         };

@@ -51,7 +51,7 @@ struct RoundState {
     int rc_count;            // worklist vertices that must be re-merged / recomputed
     int hub_count;           // the hubs among them (sampled peel: merged by wider blocks)
     int pad_hub;
-    int opt_count;           // optional recomputations appended to a batch
+    int blocks_done;         // last-block detection of the lazy exact peel's final kernel
     int mode;                // device-driven exact peel: 0 commit, 1 recompute, 2 done
     int ms_ns;               // sources of the current device-driven h-degree batch
     long long hi;            // recompute every inexact vertex whose bound is <= hi
@@ -133,24 +133,31 @@ void launch_record_fill(RoundState* st, int* hopfill, int t, hipStream_t s);
 void launch_bound_hist(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
                        hipStream_t s, const int32_t* seg = nullptr, int* shist = nullptr, int gate = 0);
 void launch_decide(RoundState* st, int cap, hipStream_t s);
-// The commit sequence of the lazy exact peel: as launch_decide, but a needed
-// recomputation stalls the sequence (st->stall) instead of picking sources;
-// the gated kernels of the sequence then do nothing until launch_unstall.
-void launch_decide_commit(RoundState* st, int cap, hipStream_t s);
+// The recompute sequence ends by lifting the stall and resetting the round state.
 // One sweep for the commit sequence: min key, alive count and the smallest
 // bound of an inexact vertex.
 void launch_reduce_hist(const int64_t* deg, const uint8_t* alive, const uint8_t* exact, int32_t n, RoundState* st,
                         hipStream_t s);
 void launch_unstall(RoundState* st, hipStream_t s);
-// Round begin folded into the selection: c = max(c, min key), rounds += 1.
+// The commit decision and the round begin folded into the selection: commit
+// when no inexact bound is at or below c' = max(c, min key) (then c = c',
+// rounds += 1, R = {key <= c}), else stall; mode 2 once nothing is alive.
 void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core,
                           int32_t* rlist, int32_t* mark, hipStream_t s);
+// For the listed R (rlist, *rcount): mode 0 sets R's mask bits (bit j for
+// rlist[j]) in rmask and gain, mode 1 removes R from the alive set; both then
+// queue R's adjacency in chunks for the next expansion (*qcount must be 0).
+void launch_enqueue_r(const int32_t* rlist, const int* rcount, const int32_t* rp, int32_t* qv, int32_t* qb, int* qcount,
+                      int mode, uint64_t* rmask, uint64_t* gain, uint8_t* alive, hipStream_t s);
 // Mask BFS bookkeeping of hop t: hopfill[t] = aff_fill, then the resets of hop
 // t + 1 (t < h) or the expansion queue (t == h).
 void launch_hop_end(RoundState* st, int* hopfill, int t, int h, hipStream_t s);
-// arr_k[list_k[i]] = 0 for three (list, count, array) triples at once.
+// arr_k[list_k[i]] = 0 for three (list, count, array) triples at once; with
+// st != NULL the last block then resets the round state for the next round
+// (unless the sequence is stalled).
 void launch_clear_u64_lists3(const int32_t* l0, const int* c0, uint64_t* a0, const int32_t* l1, const int* c1,
-                             uint64_t* a1, const int32_t* l2, const int* c2, uint64_t* a2, hipStream_t s);
+                             uint64_t* a1, const int32_t* l2, const int* c2, uint64_t* a2, hipStream_t s,
+                             RoundState* st = nullptr);
 // Picks the inexact alive vertices with deg <= st->hi as the next sources (at
 // most cap).  seg (nullable): segment (graph) of every vertex of a packed union;
 // then each source also gets a bit position sbit[slot] that is unique within its
@@ -163,7 +170,6 @@ void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact,
 void launch_decide_seg(RoundState* st, int nseg, int* shist, long long* shi, int cap, hipStream_t s);
 // R-mask BFS: after h hops rmask[v] holds bit (j mod 64) for every deleted r_j within
 // distance h of v in G[X]; first-visited vertices are appended to alist in hop order.
-void launch_rbfs_init(const int32_t* rlist, RoundState* st, uint64_t* rmask, uint64_t* gain, hipStream_t s);
 void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
                         const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
                         int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
