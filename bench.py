@@ -384,7 +384,7 @@ def main():
                     help="write profiles/traffic_counters.json from two rocprofv3 --pmc runs of this command")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

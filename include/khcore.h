@@ -42,7 +42,7 @@ typedef int32_t kh_status;
 #define KH_EOVERFLOW  (-5) /* a core number or estimate does not fit int32 */
 #define KH_EBUSY      (-6) /* a served request is still running */
 #define KH_ENOTFOUND  (-7) /* unknown ticket */
-#define KH_ENOTIMPL   (-8) /* parameters outside what this build supports (see the entry point) */
+#define KH_ENOTIMPL   (-8) /* parameters outside what this library supports (see the entry point) */
 
 /* kh_graph_load_csr flags */
 #define KH_PTRS_HOST           0u /* row_ptr/col are host memory; the library copies them */

@@ -215,7 +215,7 @@ extern "C" const char* kh_status_str(kh_status s) {
         case KH_EOVERFLOW: return "KH_EOVERFLOW: value does not fit int32";
         case KH_EBUSY: return "KH_EBUSY: request still running";
         case KH_ENOTFOUND: return "KH_ENOTFOUND: unknown ticket";
-        case KH_ENOTIMPL: return "KH_ENOTIMPL: parameters outside what this build supports";
+        case KH_ENOTIMPL: return "KH_ENOTIMPL: parameters outside what this library supports";
         default: return "unknown kh_status";
     }
 }
