@@ -18,6 +18,10 @@ public datasets which are not available here):
 * ``barabasi_albert(n, k, seed)``  -- preferential attachment, k edges per
   new vertex, seed clique K_{k+1}, targets proportional to degree without
   repetition.
+* ``sbm(n, seed)``                 -- the hierarchical stochastic block model of
+  the paper's scaling experiment (Sec. 8): 10 equal blocks, every pair of
+  vertices in blocks i < j joined with probability 1e-6 i^2, pairs inside a
+  block with probability p_in.
 * small deterministic shapes (path, cycle, star, clique, ...) for tests.
 """
 from __future__ import annotations
@@ -277,6 +281,67 @@ def barabasi_albert(n: int, k: int = 3, seed: int = 1, permute: bool = True) -> 
     return from_edges(n, e, f"ba_n{n}_k{k}_s{seed}")
 
 
+def _bernoulli_positions(key: int, total: int, p: float) -> np.ndarray:
+    """Indices in [0, total) each kept independently with probability p,
+    by geometric skips: the gap before the next kept index is
+    floor(log(1-U) / log(1-p)), which is Geometric(p) for U uniform on [0, 1)
+    (Batagelj and Brandes, "Efficient generation of large random networks",
+    Phys. Rev. E 71, 2005)."""
+    if total <= 0 or p <= 0.0:
+        return np.zeros(0, dtype=np.int64)
+    if p >= 1.0:
+        return np.arange(total, dtype=np.int64)
+    lq = math.log1p(-p)
+    out = []
+    pos = -1
+    start = 0
+    while True:
+        cnt = int(total * p * 1.1) + 64
+        u = _unit_double(splitmix_stream(key, start, cnt))
+        start += cnt
+        gap = np.floor(np.log1p(-u) / lq).astype(np.int64)
+        idx = pos + np.cumsum(gap + 1)
+        keep = idx < total
+        out.append(idx[keep])
+        if not keep.all():
+            return np.concatenate(out)
+        pos = int(idx[-1])
+
+
+def sbm(n: int, seed: int = 1, blocks: int = 10, p_in: float = 4e-4, p_scale: float = 1e-6,
+        permute: bool = True) -> Graph:
+    """Stochastic block model with hierarchical inter-block density.
+
+    Vertices are split into ``blocks`` consecutive blocks C_1..C_B of equal
+    size (the first n mod B blocks one larger).  A pair in C_i x C_j, i < j,
+    is an edge with probability p_scale * i^2; a pair inside one block with
+    probability p_in.  Every pair is drawn independently.  The inter-block
+    rule is the paper's (Sec. 8); the intra-block probability is not given
+    there, and the default 4e-4 makes the expected edge count run from
+    about 2.8e3 at n = 1e4 to about 2.8e5 at n = 1e5, the range of edges
+    that experiment plots."""
+    sizes = np.full(blocks, n // blocks, dtype=np.int64)
+    sizes[: n % blocks] += 1
+    first = np.concatenate([[0], np.cumsum(sizes)])
+    es = []
+    for i in range(blocks):
+        si = int(sizes[i])
+        for j in range(i, blocks):
+            sj = int(sizes[j])
+            p = p_in if i == j else p_scale * (i + 1) ** 2
+            idx = _bernoulli_positions(_key(seed, 0x53424D0000 + i * blocks + j), si * sj, min(p, 1.0))
+            a = idx // sj
+            b = idx % sj
+            if i == j:
+                keep = a < b          # each unordered pair once, as (a, b) with a < b
+                a, b = a[keep], b[keep]
+            es.append(np.stack([first[i] + a, first[j] + b], axis=1))
+    e = np.concatenate(es) if es else np.zeros((0, 2), np.int64)
+    if permute:
+        e = random_permutation(n, seed)[e]
+    return from_edges(n, e, f"sbm_n{n}_s{seed}")
+
+
 # ---- small deterministic shapes ---------------------------------------------
 
 def path(n: int) -> Graph:
@@ -359,4 +424,6 @@ def workload(name: str, seed: int = 1) -> Graph:
         return chung_lu(1_000_000, 10_000_000, 2.1, seed)
     if name == "cl4m":          # Chung-Lu n=4e6, m=6e7, gamma=2.3
         return chung_lu(4_000_000, 60_000_000, 2.3, seed)
+    if name.startswith("sbm"):  # sbm<n>: the block model above at n vertices
+        return sbm(int(name[3:]), seed)
     raise KeyError(name)
