@@ -351,6 +351,42 @@ def bench_cl4m(kh, ctx, args):
     return out
 
 
+def bench_sbm(kh, ctx, args):
+    """The paper's scaling experiment (Sec. 8): hierarchical block models with
+    10 equal blocks (inter-block pair probability 1e-6 i^2, intra-block 4e-4)
+    at each n in --sbm-ns, sampled Core at eps = 0.5 and h = 2, 3, 4, with
+    ExactCore beside it.  Each time is the median of --sbm-reps runs after one
+    warm-up run, graph resident on the GPU, core numbers left on the device."""
+    import torch
+
+    import graphgen as gg
+    rows = []
+    for n in [int(x) for x in args.sbm_ns.split(",")]:
+        g = gg.sbm(n, seed=1)
+        G = kh.Graph.from_gg(ctx, g)
+        out = torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda:0")
+        for h in (2, 3, 4):
+            row = {"n": n, "m": g.m, "h": h}
+            for mode, eps in (("sampled", 0.5), ("exact", 0.0)):
+                ts = []
+                for _ in range(args.sbm_reps + 1):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    _, res = kh.core(G, h, epsilon=eps, delta=0.05, seed=1, out=out)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t)
+                row[f"{mode}_ms"] = round(1e3 * sorted(ts[1:])[len(ts[1:]) // 2], 3)
+                row[f"{mode}_max_core"] = res["max_core"]
+                row[f"{mode}_rounds"] = res["rounds"]
+                if mode == "sampled":
+                    row["M_used"] = res["M_used"]
+            log(f"sbm {row}")
+            rows.append(row)
+        del G
+    return {"graph": "sbm: 10 equal blocks, p(C_i,C_j)=1e-6 i^2 (i<j), p_in=4e-4, seed 1", "eps": 0.5,
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -379,7 +415,11 @@ def main():
     ap.add_argument("--cl4m-eps", default="0.5,0.25")
     ap.add_argument("--dev-n", type=int, default=100_000)
     ap.add_argument("--dev-only", action="store_true", help="--cl4m: only the deviation study")
-    ap.add_argument("--skip-main", action="store_true", help="only the --batch / --serve / --cl4m measurements")
+    ap.add_argument("--sbm", action="store_true", help="also measure the block-model scaling series")
+    ap.add_argument("--sbm-ns", default=",".join(str(10_000 * i) for i in range(1, 11)))
+    ap.add_argument("--sbm-reps", type=int, default=3)
+    ap.add_argument("--skip-main", action="store_true",
+                    help="only the --batch / --serve / --cl4m / --sbm measurements")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_counters.json from two rocprofv3 --pmc runs of this command")
     args = ap.parse_args()
@@ -407,6 +447,8 @@ def main():
             extra["serve"] = bench_serve(kh, ctx, args)
         if args.cl4m:
             extra["cl4m"] = bench_cl4m(kh, ctx, args)
+        if args.sbm:
+            extra["sbm"] = bench_sbm(kh, ctx, args)
         print(json.dumps(extra))
         return
     t0 = time.time()
@@ -515,6 +557,8 @@ def main():
         line["serve"] = bench_serve(kh, ctx, args)
     if args.cl4m:
         line["cl4m"] = bench_cl4m(kh, ctx, args)
+    if args.sbm:
+        line["sbm"] = bench_sbm(kh, ctx, args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, hs, args.cpu_budget)
     print(json.dumps(line))
