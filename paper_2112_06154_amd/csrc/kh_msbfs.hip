@@ -431,17 +431,32 @@ __global__ __launch_bounds__(256) void k_ms_pull(int32_t nitems, const int32_t* 
             }
         }
     }
+    // Counters: one atomic per block and counter.  They all sit in one cache
+    // line, so atomics from every wave of a dense sweep queue up behind each
+    // other and cost more than the sweep itself on small graphs.
+    __shared__ unsigned long long red[5][256 / 64];
+    const int wv = threadIdx.x >> 6;
     fdeg = wave_sum_ll(fdeg);
-    if (l == 0 && fdeg) atomicAdd((unsigned long long*)&ctl->fdeg[slot], (unsigned long long)fdeg);
     te = (unsigned long long)wave_sum_ll((long long)te);
     arcs = (unsigned long long)wave_sum_ll((long long)arcs);
     bytes = (unsigned long long)wave_sum_ll((long long)bytes);
     gath = (unsigned long long)wave_sum_ll((long long)gath);
     if (l == 0) {
-        if (te) atomicAdd(&st->te, te);
-        if (arcs) atomicAdd(&st->arcs, arcs);
-        if (bytes) atomicAdd(&st->pull_bytes, bytes);
-        if (gath) atomicAdd(&st->pull_gather, gath);
+        red[0][wv] = (unsigned long long)fdeg;
+        red[1][wv] = te;
+        red[2][wv] = arcs;
+        red[3][wv] = bytes;
+        red[4][wv] = gath;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        unsigned long long v = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += red[threadIdx.x][w];
+        if (v) {
+            unsigned long long* dst[5] = {(unsigned long long*)&ctl->fdeg[slot], &st->te, &st->arcs,
+                                          &st->pull_bytes, &st->pull_gather};
+            atomicAdd(dst[threadIdx.x], v);
+        }
     }
 }
 
@@ -595,7 +610,7 @@ static void ms_batch_q(const MsPlanes& P, const MsItems& I, int32_t n, const int
         const int last = t == h ? 1 : 0;
         hipLaunchKernelGGL(k_ms_expand, dim3(exp_grid), dim3(256), 0, s, fl[(t - 1) & 1], fc[(t - 1) & 1], P.ctl, t,
                            I.nnz, rp, col, alive, P.bmC, cv[t & 1], ci[t & 1], I.vitem, ns_dev);
-        const int pull_grid = grid_for((int64_t)I.nitems * Q, 256, 16384);
+        const int pull_grid = grid_for((int64_t)I.nitems * Q, 256, 2048);
         PullTimer* T = P.timer;
         const bool timed = T && T->used < T->cap;
         if (timed) (void)hipEventRecord(T->ev[2 * T->used], s);
