@@ -202,7 +202,10 @@ kh_status kh_serve_wait(kh_context *ctx, uint64_t ticket, kh_result *res);
 kh_status kh_serve_cancel(kh_context *ctx, uint64_t ticket);
 
 /* Finish every queued request, stop the workers and drop uncollected results.
- * No call may wait on this context meanwhile.  kh_context_destroy does this too. */
+ * Serving calls may race with it: a kh_serve_wait blocked meanwhile returns
+ * its result if it was collected first, else KH_ENOTFOUND; a submission made
+ * after the stop has begun goes to a new loop that it starts.
+ * kh_context_destroy stops the loop too (no call may use the context then). */
 kh_status kh_serve_stop(kh_context *ctx);
 
 /* h-degrees deg_h(v;X) = |N(v;h,X)| - 1 (Sec. 2) of every vertex of X, where

@@ -14,6 +14,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -55,10 +56,15 @@ struct Server {
     uint64_t next_id = 1;
 };
 
+// A server lives while the map or any call in progress holds it, so a call
+// that races with kh_serve_stop never touches freed memory.  The map itself is
+// never destroyed: a server still running at process exit must not be torn
+// down (with its joinable threads) by a static destructor.
 std::mutex g_lock;
-std::unordered_map<kh_context*, Server*> g_servers;
+std::unordered_map<kh_context*, std::shared_ptr<Server>>& g_servers =
+    *new std::unordered_map<kh_context*, std::shared_ptr<Server>>();
 
-Server* find_server(kh_context* ctx) {
+std::shared_ptr<Server> find_server(kh_context* ctx) {
     std::lock_guard<std::mutex> lk(g_lock);
     auto it = g_servers.find(ctx);
     return it == g_servers.end() ? nullptr : it->second;
@@ -198,21 +204,18 @@ void worker(Server* S) {
 }
 
 kh_status start(kh_context* ctx, int32_t workers, uint64_t budget, int32_t queue_cap, int64_t batch_vertices,
-                 Server** out) {
+                 std::shared_ptr<Server>* out) {
     if (!ctx || workers < 0 || queue_cap < 0 || batch_vertices < 0) return KH_EINVAL;
     std::lock_guard<std::mutex> lk(g_lock);
     if (g_servers.count(ctx)) return KH_EBUSY;
     const int dev = kh::context_device(ctx);
     if (hipSetDevice(dev) != hipSuccess) return KH_EDEVICE;
-    Server* S = new Server();
+    auto S = std::make_shared<Server>();
     S->ctx = ctx;
     S->device = dev;
     if (budget == 0) {
         size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
-            delete S;
-            return KH_EDEVICE;
-        }
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return KH_EDEVICE;
         budget = (uint64_t)(0.8 * (double)fr);
     }
     S->budget = budget;
@@ -220,7 +223,7 @@ kh_status start(kh_context* ctx, int32_t workers, uint64_t budget, int32_t queue
     if (batch_vertices > 0) S->batch_vertices = batch_vertices;
     const int w = workers > 0 ? workers : 4;
     try {
-        for (int i = 0; i < w; ++i) S->threads.emplace_back(worker, S);
+        for (int i = 0; i < w; ++i) S->threads.emplace_back(worker, S.get());
     } catch (...) {
         {
             std::lock_guard<std::mutex> l2(S->m);
@@ -228,7 +231,6 @@ kh_status start(kh_context* ctx, int32_t workers, uint64_t budget, int32_t queue
         }
         S->cv_work.notify_all();
         for (auto& t : S->threads) t.join();
-        delete S;
         return KH_ENOMEM;
     }
     g_servers[ctx] = S;
@@ -236,6 +238,9 @@ kh_status start(kh_context* ctx, int32_t workers, uint64_t budget, int32_t queue
     return KH_OK;
 }
 
+// The workers finish every queued request before they exit; results nobody
+// collected are dropped, and a kh_serve_wait still blocked on one of them
+// wakes up to KH_ENOTFOUND.
 void stop(Server* S) {
     {
         std::lock_guard<std::mutex> lk(S->m);
@@ -243,14 +248,19 @@ void stop(Server* S) {
     }
     S->cv_work.notify_all();
     for (auto& t : S->threads) t.join();
-    for (auto& kv : S->table) delete kv.second;
-    delete S;
+    S->threads.clear();
+    {
+        std::lock_guard<std::mutex> lk(S->m);
+        for (auto& kv : S->table) delete kv.second;
+        S->table.clear();
+    }
+    S->cv_done.notify_all();
 }
 
 }  // namespace
 
 void kh::serve_shutdown(kh_context* ctx) {
-    Server* S = nullptr;
+    std::shared_ptr<Server> S;
     {
         std::lock_guard<std::mutex> lk(g_lock);
         auto it = g_servers.find(ctx);
@@ -258,12 +268,12 @@ void kh::serve_shutdown(kh_context* ctx) {
         S = it->second;
         g_servers.erase(it);
     }
-    stop(S);
+    stop(S.get());
 }
 
 extern "C" kh_status kh_serve_start(kh_context* ctx, int32_t workers, uint64_t hbm_budget_bytes, int32_t queue_cap,
                                     int64_t batch_vertices) {
-    Server* S = nullptr;
+    std::shared_ptr<Server> S;
     return start(ctx, workers, hbm_budget_bytes, queue_cap, batch_vertices, &S);
 }
 
@@ -275,7 +285,7 @@ extern "C" kh_status kh_serve_submit(kh_context* ctx, kh_graph* g, const kh_para
         return KH_EINVAL;
     const int32_t n = kh_graph_n(g);
     if (n > 0 && !core_out) return KH_EINVAL;
-    Server* S = find_server(ctx);
+    std::shared_ptr<Server> S = find_server(ctx);
     if (!S) {
         const kh_status st = start(ctx, 0, 0, 0, 0, &S);
         if (st == KH_EBUSY) S = find_server(ctx);  // started meanwhile by another thread
@@ -311,11 +321,18 @@ kh_status collect(Server* S, uint64_t ticket, kh_result* res, bool wait) {
     std::unique_lock<std::mutex> lk(S->m);
     auto it = S->table.find(ticket);
     if (it == S->table.end()) return KH_ENOTFOUND;
-    Request* r = it->second;
-    if (!r->done) {
+    if (!it->second->done) {
         if (!wait) return KH_EBUSY;
-        S->cv_done.wait(lk, [&] { return r->done; });
+        // look the ticket up again after every wake-up: another caller may have
+        // collected it, or a stop dropped it, while this one slept
+        S->cv_done.wait(lk, [&] {
+            auto jt = S->table.find(ticket);
+            return jt == S->table.end() || jt->second->done;
+        });
+        it = S->table.find(ticket);
+        if (it == S->table.end()) return KH_ENOTFOUND;
     }
+    Request* r = it->second;
     const kh_status st = r->status;
     if (res) *res = r->res;
     S->table.erase(ticket);
@@ -326,21 +343,21 @@ kh_status collect(Server* S, uint64_t ticket, kh_result* res, bool wait) {
 
 extern "C" kh_status kh_serve_poll(kh_context* ctx, uint64_t ticket, kh_result* res) {
     if (!ctx) return KH_EINVAL;
-    Server* S = find_server(ctx);
+    std::shared_ptr<Server> S = find_server(ctx);
     if (!S) return KH_ENOTFOUND;
-    return collect(S, ticket, res, false);
+    return collect(S.get(), ticket, res, false);
 }
 
 extern "C" kh_status kh_serve_wait(kh_context* ctx, uint64_t ticket, kh_result* res) {
     if (!ctx) return KH_EINVAL;
-    Server* S = find_server(ctx);
+    std::shared_ptr<Server> S = find_server(ctx);
     if (!S) return KH_ENOTFOUND;
-    return collect(S, ticket, res, true);
+    return collect(S.get(), ticket, res, true);
 }
 
 extern "C" kh_status kh_serve_cancel(kh_context* ctx, uint64_t ticket) {
     if (!ctx) return KH_EINVAL;
-    Server* S = find_server(ctx);
+    std::shared_ptr<Server> S = find_server(ctx);
     if (!S) return KH_ENOTFOUND;
     std::lock_guard<std::mutex> lk(S->m);
     auto it = S->table.find(ticket);

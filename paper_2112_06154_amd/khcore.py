@@ -323,10 +323,12 @@ class Server:
     def _collect(self, ticket: int, wait: bool):
         res = Result()
         fn = lib().kh_serve_wait if wait else lib().kh_serve_poll
+        # hold the output while the call runs: a concurrent stop() forgets it
+        out, graph = self._pending.get(ticket, (None, None))
         code = fn(self.ctx.handle, ticket, ctypes.byref(res))
         if code == KH_EBUSY:
             return None
-        out, graph = self._pending.pop(ticket, (None, None))
+        self._pending.pop(ticket, None)
         _check(code, "kh_serve_wait" if wait else "kh_serve_poll")
         if isinstance(out, np.ndarray):
             out = out[:graph.n]

@@ -182,3 +182,41 @@ def test_concurrent_calls_on_one_context(ctx):
     assert not errors
     for g, w, c in zip(gs, want, got):
         assert np.array_equal(c, w), g.name
+
+
+def test_stop_while_callers_wait(ctx):
+    # kh_serve_stop finishes the queued requests; a kh_serve_wait blocked
+    # meanwhile returns its result or, if the stop dropped it first,
+    # KH_ENOTFOUND -- never a crash.  A new loop can start afterwards.
+    import threading
+    gs = pool(4, seed=5)
+    Gs = [kh.Graph.from_gg(ctx, g) for g in gs]
+    want = {gi: kh.core(Gs[gi], 2)[0] for gi in range(4)}
+    S = kh.Server(ctx, workers=1)
+    tickets = [(S.submit(Gs[i % 4], 2), i % 4) for i in range(12)]
+    got = {}
+
+    def waiter(t, gi):
+        try:
+            got[t] = ("ok", S.wait(t)[0], gi)
+        except kh.KhError as e:
+            got[t] = ("err", e.code, gi)
+
+    ths = [threading.Thread(target=waiter, args=tg) for tg in tickets[-4:]]
+    for th in ths:
+        th.start()
+    say("stop while waiting")
+    S.stop()
+    for th in ths:
+        th.join(timeout=60)
+        assert not th.is_alive()
+    assert len(got) == 4
+    for kind, val, gi in got.values():
+        if kind == "ok":
+            assert np.array_equal(val, want[gi])
+        else:
+            assert val == kh.khcore.KH_ENOTFOUND
+    S2 = kh.Server(ctx, workers=2)
+    t = S2.submit(Gs[1], 2)
+    assert np.array_equal(S2.wait(t)[0], want[1])
+    S2.stop()
