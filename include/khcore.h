@@ -203,8 +203,9 @@ kh_status kh_serve_cancel(kh_context *ctx, uint64_t ticket);
 
 /* Finish every queued request, stop the workers and drop uncollected results.
  * Serving calls may race with it: a kh_serve_wait blocked meanwhile returns
- * its result if it was collected first, else KH_ENOTFOUND; a submission made
- * after the stop has begun goes to a new loop that it starts.
+ * its result if its request finished before the results were dropped, else
+ * KH_ENOTFOUND; a submission racing with the stop gets KH_EBUSY or starts a
+ * new loop.
  * kh_context_destroy stops the loop too (no call may use the context then). */
 kh_status kh_serve_stop(kh_context *ctx);
 
