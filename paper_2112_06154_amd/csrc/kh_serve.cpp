@@ -203,6 +203,8 @@ void worker(Server* S) {
     if (stream) (void)hipStreamDestroy(stream);
 }
 
+void stop(Server* S);
+
 kh_status start(kh_context* ctx, int32_t workers, uint64_t budget, int32_t queue_cap, int64_t batch_vertices,
                  std::shared_ptr<Server>* out) {
     if (!ctx || workers < 0 || queue_cap < 0 || batch_vertices < 0) return KH_EINVAL;
@@ -233,7 +235,12 @@ kh_status start(kh_context* ctx, int32_t workers, uint64_t budget, int32_t queue
         for (auto& t : S->threads) t.join();
         return KH_ENOMEM;
     }
-    g_servers[ctx] = S;
+    try {
+        g_servers[ctx] = S;
+    } catch (...) {
+        stop(S.get());
+        return KH_ENOMEM;
+    }
     *out = S;
     return KH_OK;
 }
@@ -274,7 +281,11 @@ void kh::serve_shutdown(kh_context* ctx) {
 extern "C" kh_status kh_serve_start(kh_context* ctx, int32_t workers, uint64_t hbm_budget_bytes, int32_t queue_cap,
                                     int64_t batch_vertices) {
     std::shared_ptr<Server> S;
-    return start(ctx, workers, hbm_budget_bytes, queue_cap, batch_vertices, &S);
+    try {
+        return start(ctx, workers, hbm_budget_bytes, queue_cap, batch_vertices, &S);
+    } catch (...) {
+        return KH_ENOMEM;
+    }
 }
 
 extern "C" kh_status kh_serve_submit(kh_context* ctx, kh_graph* g, const kh_params* params, int32_t* core_out,
@@ -285,35 +296,43 @@ extern "C" kh_status kh_serve_submit(kh_context* ctx, kh_graph* g, const kh_para
         return KH_EINVAL;
     const int32_t n = kh_graph_n(g);
     if (n > 0 && !core_out) return KH_EINVAL;
-    std::shared_ptr<Server> S = find_server(ctx);
-    if (!S) {
-        const kh_status st = start(ctx, 0, 0, 0, 0, &S);
-        if (st == KH_EBUSY) S = find_server(ctx);  // started meanwhile by another thread
-        else if (st != KH_OK) return st;
-        if (!S) return KH_EDEVICE;
-    }
-    Request* r = new (std::nothrow) Request();
-    if (!r) return KH_ENOMEM;
-    r->g = g;
-    r->p = *params;
-    r->out = core_out;
-    r->n = n;
-    r->nnz = kh_graph_nnz(g);
-    r->est = estimate_bytes(*r);
-    r->t_submit = Clock::now();
-    {
-        std::lock_guard<std::mutex> lk(S->m);
-        if (S->stopping || (int)S->queue.size() >= S->queue_cap) {
-            delete r;
-            return KH_EBUSY;
+    try {
+        std::shared_ptr<Server> S = find_server(ctx);
+        if (!S) {
+            const kh_status st = start(ctx, 0, 0, 0, 0, &S);
+            if (st == KH_EBUSY) S = find_server(ctx);  // started meanwhile by another thread
+            else if (st != KH_OK) return st;
+            if (!S) return KH_EDEVICE;
         }
-        r->id = S->next_id++;
-        S->queue.push_back(r);
-        S->table[r->id] = r;
-        *ticket = r->id;
+        std::unique_ptr<Request> r(new Request());
+        r->g = g;
+        r->p = *params;
+        r->out = core_out;
+        r->n = n;
+        r->nnz = kh_graph_nnz(g);
+        r->est = estimate_bytes(*r);
+        r->t_submit = Clock::now();
+        {
+            std::lock_guard<std::mutex> lk(S->m);
+            if (S->stopping || (int)S->queue.size() >= S->queue_cap) return KH_EBUSY;
+            const uint64_t id = S->next_id;
+            S->table[id] = r.get();
+            try {
+                S->queue.push_back(r.get());
+            } catch (...) {
+                S->table.erase(id);
+                throw;
+            }
+            S->next_id += 1;
+            r->id = id;
+            *ticket = id;
+            r.release();  // owned by the table from here on
+        }
+        S->cv_work.notify_one();
+        return KH_OK;
+    } catch (...) {
+        return KH_ENOMEM;
     }
-    S->cv_work.notify_one();
-    return KH_OK;
 }
 
 namespace {
