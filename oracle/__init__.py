@@ -61,9 +61,9 @@ def lib():
         L.orc_hdeg_list.restype = ci
         L.orc_est_all.argtypes = [i64, P, P, P, ci, P, i64, P]
         L.orc_est_all.restype = ci
-        L.orc_exact_core.argtypes = [i64, P, P, ci, u64, P, P, P]
+        L.orc_exact_core.argtypes = [i64, P, P, ci, u64, ci, P, P, P]
         L.orc_exact_core.restype = ci
-        L.orc_sampled_core.argtypes = [i64, P, P, ci, P, i64, u64, P, P]
+        L.orc_sampled_core.argtypes = [i64, P, P, ci, P, i64, u64, ci, P, P]
         L.orc_sampled_core.restype = ci
         L.orc_exact_core_sweep.argtypes = [i64, P, P, ci, P]
         L.orc_exact_core_sweep.restype = ci
@@ -71,6 +71,10 @@ def lib():
         L.orc_sampled_lists.restype = i64
         L.orc_dense.argtypes = [i64, P, P, P, ci, ci, P, i64, ci, dbl, P, P, P, P, P, P, P]
         L.orc_dense.restype = ci
+        L.orc_bulk_order.argtypes = [i64, P, P, P, ci, ci, P, i64, P, P, P]
+        L.orc_bulk_order.restype = i64
+        L.orc_dense_suffix.argtypes = [i64, P, P, ci, ci, P, i64, i64, P, P, P]
+        L.orc_dense_suffix.restype = ci
         _lib = L
     return _lib
 
@@ -154,14 +158,17 @@ def estimate_all(g, h: int, r, M: int, alive=None) -> np.ndarray:
     return out[:g.n]
 
 
-def exact_core(g, h: int, tie_seed: int = 0, with_order: bool = False, with_te: bool = False):
-    """ExactCore (Sec. 2): sequential min-peel on deg_h, running maximum."""
+def exact_core(g, h: int, tie_seed: int = 0, with_order: bool = False, with_te: bool = False,
+               early_stop: bool = False):
+    """ExactCore (Sec. 2): sequential min-peel on deg_h, running maximum.
+    early_stop: the Sec. 5 heuristic (stop once c + 1 >= remaining)."""
     rp, col = _csr(g)
     core = np.zeros(max(g.n, 1), np.int64)
     order = np.zeros(max(g.n, 1), np.int32)
     te = ctypes.c_int64(0)
     if g.n:
-        lib().orc_exact_core(g.n, _p(rp), _p(col), h, tie_seed, _p(core), _p(order), ctypes.byref(te))
+        lib().orc_exact_core(g.n, _p(rp), _p(col), h, tie_seed, int(early_stop), _p(core), _p(order),
+                             ctypes.byref(te))
     res = [core[:g.n]]
     if with_order:
         res.append(order[:g.n])
@@ -178,8 +185,9 @@ def exact_core_sweep(g, h: int) -> np.ndarray:
     return core[:g.n]
 
 
-def sampled_core(g, h: int, r, M: int, tie_seed: int = 0, with_order: bool = False):
-    """Core (Alg. 4) through the closed form of its estimate."""
+def sampled_core(g, h: int, r, M: int, tie_seed: int = 0, with_order: bool = False, early_stop: bool = False):
+    """Core (Alg. 4) through the closed form of its estimate.
+    early_stop: the Sec. 5 heuristic (stop once c + 1 >= remaining)."""
     rp, col = _csr(g)
     rr = np.ascontiguousarray(r, dtype=np.uint8)
     if rr.size == 0:
@@ -187,7 +195,7 @@ def sampled_core(g, h: int, r, M: int, tie_seed: int = 0, with_order: bool = Fal
     core = np.zeros(max(g.n, 1), np.int64)
     order = np.zeros(max(g.n, 1), np.int32)
     if g.n:
-        lib().orc_sampled_core(g.n, _p(rp), _p(col), h, _p(rr), M, tie_seed, _p(core), _p(order))
+        lib().orc_sampled_core(g.n, _p(rp), _p(col), h, _p(rr), M, tie_seed, int(early_stop), _p(core), _p(order))
     return (core[:g.n], order[:g.n]) if with_order else core[:g.n]
 
 
@@ -230,3 +238,38 @@ def dense(g, core, h: int, mode: str = "exact", r=None, M: int = 0, prune: bool 
     cands = [(int(ck[i]), int(cs[i]), int(cR[i])) for i in range(nc.value)]
     return {"k": bk.value, "size": bs.value, "R": bR.value,
             "density": (bR.value / (2.0 * bs.value)) if bs.value else 0.0, "cands": cands}
+
+
+def bulk_order(g, h: int, mode: str = "exact", r=None, M: int = 0, alive=None):
+    """Deletion order of the bulk-round peel (rounds in sequence; inside a
+    round by (f, level of Def. est, id)), with the core numbers and the round
+    of every deletion.  Returns (order int32[count], core int64[n], round int64[n])."""
+    rp, col = _csr(g)
+    rr = np.ascontiguousarray(r if r is not None else np.zeros(max(g.n, 1), np.uint8), dtype=np.uint8)
+    order = np.zeros(max(g.n, 1), np.int32)
+    core = np.zeros(max(g.n, 1), np.int64)
+    rnd = np.zeros(max(g.n, 1), np.int64)
+    cnt = 0
+    if g.n:
+        cnt = lib().orc_bulk_order(g.n, _p(rp), _p(col), _p(_alive(g, alive)), h, 0 if mode == "exact" else 1,
+                                   _p(rr), M, _p(order), _p(core), _p(rnd))
+    return order[:cnt], core[:g.n], rnd[:g.n]
+
+
+def dense_suffix(g, order, h: int, mode: str = "exact", r=None, M: int = 0):
+    """Alg. 7 over every suffix of `order`: R[i] = sum of f over the suffix
+    starting at i, measured inside it.  Returns dict with R (int64[count]),
+    the best start index (ties: later), its size, R and density R/(2 size)."""
+    rp, col = _csr(g)
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    cnt = int(o.size)
+    if cnt == 0:
+        return {"R": np.zeros(0, np.int64), "best": -1, "size": 0, "best_R": 0, "density": 0.0}
+    rr = np.ascontiguousarray(r if r is not None else np.zeros(max(g.n, 1), np.uint8), dtype=np.uint8)
+    R = np.zeros(cnt, np.int64)
+    bi = ctypes.c_int64(-1)
+    lib().orc_dense_suffix(g.n, _p(rp), _p(col), h, 0 if mode == "exact" else 1, _p(rr), M, cnt, _p(o), _p(R),
+                           ctypes.byref(bi))
+    b = bi.value
+    size = cnt - b
+    return {"R": R, "best": b, "size": size, "best_R": int(R[b]), "density": R[b] / (2.0 * size)}

@@ -247,8 +247,14 @@ ORC_API int orc_est_all(int64_t n, const int32_t *rp, const int32_t *col, const 
 /* so only those are recomputed.  order_out (nullable) receives the deletion */
 /* order and fval_out (nullable) the value f(u;X) at deletion.               */
 /* ------------------------------------------------------------------------ */
+/* Early stop (Sec. 5, second heuristic; Sec. 8 states the test as "current  */
+/* core value plus one equals the number of remaining nodes"): right after a */
+/* deletion, if c + 1 >= |X| for the remaining set X, every remaining vertex */
+/* receives c and the peel ends.  For deg_h this changes nothing (every      */
+/* remaining vertex has deg_h <= |X| - 1 <= c and would leave next at c);    */
+/* for the estimate it may, since Delta can exceed |X| - 1.                  */
 static int peel(int64_t n, const int32_t *rp, const int32_t *col, const uint8_t *alive_in, int h,
-                int mode, const uint8_t *r, int64_t M, uint64_t tie_seed, int64_t *core_out,
+                int mode, const uint8_t *r, int64_t M, uint64_t tie_seed, int early_stop, int64_t *core_out,
                 int32_t *order_out, int64_t *fval_out, int64_t *te_out)
 {
     orc_ws ws;
@@ -282,6 +288,18 @@ static int peel(int64_t n, const int32_t *rp, const int32_t *col, const uint8_t 
         int64_t na = ball_of(u, h, rp, col, alive, ws.mark, aff, NULL);
         alive[u] = 0;
         remaining--;
+        if (early_stop && remaining > 0 && c + 1 >= remaining) {
+            for (int64_t v = 0; v < n; v++) {
+                if (!alive[v]) continue;
+                core_out[v] = c;
+                if (order_out) order_out[step] = (int32_t)v;
+                if (fval_out) fval_out[step] = f[v];
+                step++;
+                alive[v] = 0;
+            }
+            remaining = 0;
+            break;
+        }
         for (int64_t i = 1; i < na; i++)
             f[aff[i]] = vertex_fn(&ws, aff[i], h, alive, mode, r, M, &te);
     }
@@ -295,15 +313,15 @@ static int peel(int64_t n, const int32_t *rp, const int32_t *col, const uint8_t 
 }
 
 ORC_API int orc_exact_core(int64_t n, const int32_t *rp, const int32_t *col, int h, uint64_t tie_seed,
-                           int64_t *core_out, int32_t *order_out, int64_t *te_out)
+                           int early_stop, int64_t *core_out, int32_t *order_out, int64_t *te_out)
 {
-    return peel(n, rp, col, NULL, h, 0, NULL, 0, tie_seed, core_out, order_out, NULL, te_out);
+    return peel(n, rp, col, NULL, h, 0, NULL, 0, tie_seed, early_stop, core_out, order_out, NULL, te_out);
 }
 
 ORC_API int orc_sampled_core(int64_t n, const int32_t *rp, const int32_t *col, int h, const uint8_t *r,
-                             int64_t M, uint64_t tie_seed, int64_t *core_out, int32_t *order_out)
+                             int64_t M, uint64_t tie_seed, int early_stop, int64_t *core_out, int32_t *order_out)
 {
-    return peel(n, rp, col, NULL, h, 1, r, M, tie_seed, core_out, order_out, NULL, NULL);
+    return peel(n, rp, col, NULL, h, 1, r, M, tie_seed, early_stop, core_out, order_out, NULL, NULL);
 }
 
 /* Second exact oracle (test-only cross-check): level sweep.  For k = 0,1,...
@@ -452,6 +470,178 @@ ORC_API int orc_dense(int64_t n, const int32_t *rp, const int32_t *col, const in
     }
     if (ncand) *ncand = nc;
     free(alive);
+    ws_free(&ws);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Full EstDense (Alg. 7): every suffix of a deletion order as a candidate.  */
+/*                                                                           */
+/* The order is the one the library's bulk-round peel deletes in (the order  */
+/* Alg. 7 takes from Core).  Round j of the peel: c = max(c, min f over X);  */
+/* R_j = {v in X : f(v;X) <= c}, listed by (f(v;X), lev(v;X), id) ascending, */
+/* where lev is the level k of Def. est for the estimate (the paper's tie    */
+/* key k[v,h] of Alg. 4) and 0 for deg_h; then X <- X \ R_j.  Every core set */
+/* {c >= K} is a suffix of this order, which is all that Prop. dense's proof */
+/* uses of the order.                                                        */
+/* ------------------------------------------------------------------------ */
+static int64_t est_level(const int32_t *x, int64_t d, int64_t M)
+{
+    int64_t k = 0;
+    for (;;) {
+        int64_t S = 0;
+        for (int64_t j = 0; j < d; j++)
+            if (x[j] >= k) S++;
+        if (S <= M) return k;
+        k++;
+    }
+}
+
+/* f(v;X) as vertex_fn, and lev(v;X) into *lev. */
+static int64_t vertex_fn_lev(orc_ws *ws, int64_t v, int h, const uint8_t *alive, int mode, const uint8_t *r,
+                             int64_t M, int64_t *lev)
+{
+    int64_t cnt = ball_of(v, h, ws->rp, ws->col, alive, ws->mark, ws->ball, NULL);
+    if (mode == 0) {
+        *lev = 0;
+        return cnt - 1;
+    }
+    for (int64_t i = 0; i < cnt; i++) ws->xr[i] = r[ws->ball[i]];
+    *lev = est_level(ws->xr, cnt, M);
+    return orc_delta(ws->xr, cnt, M);
+}
+
+typedef struct {
+    int64_t f, lev;
+    int32_t id;
+} orc_okey;
+
+static int cmp_okey(const void *a, const void *b)
+{
+    const orc_okey *x = (const orc_okey *)a, *y = (const orc_okey *)b;
+    if (x->f != y->f) return x->f < y->f ? -1 : 1;
+    if (x->lev != y->lev) return x->lev < y->lev ? -1 : 1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+/* Bulk-round deletion order of X = alive_in (NULL: V).  order_out[count]
+ * receives the order, core_out[n] the core numbers (-1 outside X) and
+ * round_out[n] (nullable) the round of each deletion.  Returns the count. */
+ORC_API int64_t orc_bulk_order(int64_t n, const int32_t *rp, const int32_t *col, const uint8_t *alive_in, int h,
+                               int mode, const uint8_t *r, int64_t M, int32_t *order_out, int64_t *core_out,
+                               int64_t *round_out)
+{
+    orc_ws ws;
+    if (ws_init(&ws, n, rp, col)) return -1;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    uint8_t *alive = (uint8_t *)malloc(nn);
+    uint8_t *aff = (uint8_t *)calloc(nn, 1);
+    int64_t *f = (int64_t *)malloc(sizeof(int64_t) * nn);
+    int64_t *lev = (int64_t *)malloc(sizeof(int64_t) * nn);
+    orc_okey *R = (orc_okey *)malloc(sizeof(orc_okey) * nn);
+    int32_t *ball = (int32_t *)malloc(sizeof(int32_t) * nn);
+    if (!alive || !aff || !f || !lev || !R || !ball) return -1;
+    int64_t remaining = 0;
+    for (int64_t v = 0; v < n; v++) {
+        alive[v] = alive_in ? (alive_in[v] != 0) : 1;
+        remaining += alive[v];
+        core_out[v] = -1;
+        if (round_out) round_out[v] = -1;
+    }
+    for (int64_t v = 0; v < n; v++)
+        if (alive[v]) f[v] = vertex_fn_lev(&ws, v, h, alive, mode, r, M, &lev[v]);
+    int64_t c = -1, pos = 0, round = 0;
+    while (remaining > 0) {
+        int64_t mn = -1;
+        for (int64_t v = 0; v < n; v++)
+            if (alive[v] && (mn < 0 || f[v] < mn)) mn = f[v];
+        if (mn > c) c = mn;
+        int64_t nr = 0;
+        for (int64_t v = 0; v < n; v++)
+            if (alive[v] && f[v] <= c) {
+                R[nr].f = f[v];
+                R[nr].lev = lev[v];
+                R[nr].id = (int32_t)v;
+                nr++;
+            }
+        qsort(R, (size_t)nr, sizeof(orc_okey), cmp_okey);
+        /* the vertices whose f can change: the h-balls of R, measured in X */
+        for (int64_t i = 0; i < nr; i++) {
+            int64_t nb = ball_of(R[i].id, h, rp, col, alive, ws.mark, ball, NULL);
+            for (int64_t j = 0; j < nb; j++) aff[ball[j]] = 1;
+        }
+        for (int64_t i = 0; i < nr; i++) {
+            int32_t u = R[i].id;
+            order_out[pos++] = u;
+            core_out[u] = c;
+            if (round_out) round_out[u] = round;
+            alive[u] = 0;
+        }
+        remaining -= nr;
+        for (int64_t v = 0; v < n; v++)
+            if (aff[v]) {
+                aff[v] = 0;
+                if (alive[v]) f[v] = vertex_fn_lev(&ws, v, h, alive, mode, r, M, &lev[v]);
+            }
+        round++;
+    }
+    free(alive);
+    free(aff);
+    free(f);
+    free(lev);
+    free(R);
+    free(ball);
+    ws_free(&ws);
+    return pos;
+}
+
+/* Alg. 7's loop over a given order v_1..v_count of the vertex set S_1 (the
+ * vertices listed; every other vertex is absent throughout).  For the suffix
+ * S_i = {v_i, ..., v_count}: R_out[i-1] = sum over v in S_i of f(v; S_i), with
+ * f = deg_h (mode 0; then R_i = 2|E_h(S_i)|) or the estimate with ranks r and
+ * buffer M (mode 1; Alg. 7 uses fresh ranks and M from C = log(n^2/delta)).
+ * R is kept up to date as Alg. 7 does: deleting v_i changes f only inside its
+ * h-ball, measured before the deletion.  The best suffix maximises
+ * R_i / |S_i| (ties: the later suffix, i.e. the smaller set); its start
+ * index (0-based) goes to *best_i.  Returns 0. */
+ORC_API int orc_dense_suffix(int64_t n, const int32_t *rp, const int32_t *col, int h, int mode, const uint8_t *r,
+                             int64_t M, int64_t count, const int32_t *order, int64_t *R_out, int64_t *best_i)
+{
+    orc_ws ws;
+    if (ws_init(&ws, n, rp, col)) return -1;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    uint8_t *alive = (uint8_t *)calloc(nn, 1);
+    int64_t *f = (int64_t *)malloc(sizeof(int64_t) * nn);
+    int32_t *ball = (int32_t *)malloc(sizeof(int32_t) * nn);
+    if (!alive || !f || !ball) return -1;
+    for (int64_t i = 0; i < count; i++) alive[order[i]] = 1;
+    int64_t R = 0;
+    for (int64_t i = 0; i < count; i++) {
+        int32_t v = order[i];
+        f[v] = vertex_fn(&ws, v, h, alive, mode, r, M, NULL);
+        R += f[v];
+    }
+    *best_i = -1;
+    for (int64_t i = 0; i < count; i++) {
+        R_out[i] = R;
+        int64_t size = count - i;
+        if (*best_i < 0 ||
+            (__int128)R * (__int128)(count - *best_i) >= (__int128)R_out[*best_i] * (__int128)size)
+            *best_i = i;
+        int32_t u = order[i];
+        int64_t nb = ball_of(u, h, rp, col, alive, ws.mark, ball, NULL);
+        R -= f[u];
+        alive[u] = 0;
+        for (int64_t j = 1; j < nb; j++) {
+            int32_t a = ball[j];
+            R -= f[a];
+            f[a] = vertex_fn(&ws, a, h, alive, mode, r, M, NULL);
+            R += f[a];
+        }
+    }
+    free(alive);
+    free(f);
+    free(ball);
     ws_free(&ws);
     return 0;
 }

@@ -6,6 +6,7 @@ examples of Def. est, a graph library (networkx), brute force over all
 vertex subsets of tiny graphs, closed forms, and the paper's propositions.
 """
 import math
+from fractions import Fraction
 
 import networkx as nx
 import numpy as np
@@ -35,6 +36,16 @@ def test_M_reproduces_table1():
     assert len(rows) == 8
     for name, n, printed in rows:
         assert oracle.M_int(int(n), 0.5, 0.05) == int(printed), name
+
+
+def test_M_dense_is_M_of_half_n_squared():
+    # Alg. 7 sets C = log(n^2/delta); Eq. (buffer) for Alg. 4 has C = log(2N/delta).
+    # So the dense M of n equals the Table-1-pinned M of N = n^2/2 (even n): a
+    # wrong constant in either C (e.g. log(2n^2/delta)) breaks the identity.
+    for n in (2, 10, 1000, 12008, 1_000_000, 4_000_000):
+        for eps in (0.25, 0.5, 0.9):
+            assert oracle.M_real(n, eps, 0.05, dense=True) == oracle.M_real(n * n // 2, eps, 0.05, dense=False)
+            assert oracle.M_int(n, eps, 0.05, dense=True) == oracle.M_int(n * n // 2, eps, 0.05, dense=False)
 
 
 def test_M_dense_uses_log_n2_over_delta():
@@ -139,6 +150,24 @@ def test_hdeg_matches_networkx(seed):
                 assert deg[v] == expect
             else:
                 assert deg[v] == -1
+
+
+def test_hdeg_list_equals_hdeg_all_on_permuted_sources():
+    # the per-source entry point returns, in the order given, the values of the
+    # all-vertex pass (itself pinned to networkx above), dead sources as -1
+    g = gg.chung_lu(500, 2500, 2.2, seed=3)
+    rng = np.random.default_rng(5)
+    alive = (rng.random(g.n) < 0.9).astype(np.uint8)
+    for h in (1, 2, 3):
+        full, te_full = oracle.hdeg(g, h, alive, with_te=True)
+        src = rng.permutation(g.n)[:137].astype(np.int32)
+        got, te = oracle.hdeg_list(g, h, src, alive, with_te=True)
+        assert np.array_equal(got, full[src])
+        # all sources in any order: same values and the same edges-traversed total
+        perm = rng.permutation(g.n).astype(np.int32)
+        got_all, te_all = oracle.hdeg_list(g, h, perm, alive, with_te=True)
+        assert np.array_equal(got_all, full[perm])
+        assert te_all == te_full
 
 
 def test_edges_traversed_count():
@@ -349,10 +378,142 @@ def test_dense_sampled_equals_exact_when_M_ge_n():
 
 
 def test_dense_prune_keeps_top_levels():
-    g = gg.barabasi_albert(200, 3, seed=3)
-    c = oracle.exact_core(g, 2)
-    full = oracle.dense(g, c, 2, "exact")
-    pr = oracle.dense(g, c, 2, "exact", prune=True, eps=0.5)
-    kmax = int(c.max())
-    assert all(K * 1.5 >= 0.5 * kmax for K, _, _ in pr["cands"])
-    assert set(pr["cands"]) <= set(full["cands"])
+    # end of Sec. 6: the pruning variant drops exactly the levels K below
+    # gamma k' (gamma = (1-eps)/(1+eps), k' = max core) and keeps every other
+    # candidate unchanged (each candidate's sum is measured inside F_K alone)
+    for eps in (0.25, 0.5):
+        for seed, h in ((3, 2), (4, 3), (5, 2)):
+            g = gg.disjoint_union(gg.clique(25), gg.erdos_renyi(150, 300, seed=seed),
+                                  gg.barabasi_albert(80, 3, seed=seed))
+            c = oracle.exact_core(g, h)
+            kmax = int(c.max())
+            full = oracle.dense(g, c, h, "exact")
+            pr = oracle.dense(g, c, h, "exact", prune=True, eps=eps)
+            keep = [t for t in full["cands"] if t[0] * (1 + eps) >= (1 - eps) * kmax]
+            assert pr["cands"] == keep
+            assert len(keep) < len(full["cands"])  # pruning removes levels here
+            best = max(keep, key=lambda t: (Fraction(t[2], t[1]), t[0]))
+            assert (pr["k"], pr["size"], pr["R"]) == best
+
+
+# ---- early stop (Sec. 5 heuristic) -------------------------------------------------
+
+def test_early_stop_worked_example():
+    g = gg.from_edges(5, [(0, 1), (1, 2), (1, 3), (1, 4), (2, 3), (2, 4), (3, 4)])
+    r = np.array([3, 2, 5, 5, 5], np.uint8)
+    for row in golden_rows("early_stop_example.txt"):
+        mode, es, want = row[0], bool(int(row[1])), [int(x) for x in row[2:]]
+        if mode == "sampled":
+            got = oracle.sampled_core(g, 1, r, 1, early_stop=es)
+        else:
+            got = oracle.exact_core(g, 1, early_stop=es)
+        assert list(got) == want, (mode, es)
+
+
+def early_stop_closed_form(core):
+    """Derived from the peel: vertices leave in non-decreasing core order, the
+    test c + 1 >= |X| is weakest at the end of each level's deletions, where
+    |X| = #{core > c}; so the first level c with c + 1 >= #{core > c} stops the
+    peel and every vertex gets min(core, c)."""
+    core = np.asarray(core)
+    for c in np.unique(core):
+        if c + 1 >= int((core > c).sum()):
+            return np.minimum(core, c)
+    return core
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_early_stop_closed_form_and_exact_safety(seed):
+    g = gg.chung_lu(60, 200, 2.2, seed=seed) if seed % 2 else gg.erdos_renyi(40, 120, seed=seed)
+    r = oracle.ranks(g.n, seed)
+    changed = 0
+    for h in (2, 3):
+        # exact: deg_h <= |X| - 1, so stopping never changes a core number
+        c = oracle.exact_core(g, h)
+        assert np.array_equal(oracle.exact_core(g, h, early_stop=True), c)
+        assert np.array_equal(early_stop_closed_form(c), c)
+        for M in (1, 2, 3, 5):
+            cp = oracle.sampled_core(g, h, r, M)
+            es = oracle.sampled_core(g, h, r, M, early_stop=True)
+            assert np.array_equal(es, early_stop_closed_form(cp)), (h, M)
+            changed += int((es != cp).any())
+            # tie-breaks still do not matter
+            assert np.array_equal(oracle.sampled_core(g, h, r, M, tie_seed=77, early_stop=True), es)
+    if seed in (2, 3):
+        assert changed > 0  # the heuristic does change sampled outputs here
+
+
+# ---- full EstDense (Alg. 7 over every suffix of the deletion order) --------------------
+
+def _round_starts(rnd):
+    return sorted(set(rnd.tolist()))
+
+
+@pytest.mark.parametrize("mode", ["exact", "sampled"])
+def test_bulk_order_is_the_bulk_peel(mode):
+    # rounds of the bulk peel, checked from their plain definition with the
+    # (separately pinned) h-degree and estimate: at the start of round j with
+    # alive set X_j, c_j = max(c_{j-1}, min f), R_j = {f <= c_j}, listed by
+    # (f, level, id); the order's core numbers equal the sequential peel's.
+    g = gg.chung_lu(250, 1000, 2.2, seed=7)
+    h, M = 2, 6
+    r = oracle.ranks(g.n, 3)
+    order, core, rnd = oracle.bulk_order(g, h, mode, r, M)
+    assert sorted(order.tolist()) == list(range(g.n))
+    want = oracle.exact_core(g, h) if mode == "exact" else oracle.sampled_core(g, h, r, M)
+    assert np.array_equal(core, want)
+    assert np.all(np.diff(rnd[order]) >= 0)
+    c = -1
+    for j in _round_starts(rnd):
+        X = (rnd >= j).astype(np.uint8)
+        f = oracle.hdeg(g, h, X) if mode == "exact" else oracle.estimate_all(g, h, r, M, X)
+        c = max(c, int(f[X == 1].min()))
+        R = [v for v in order if rnd[v] == j]
+        assert set(R) == {v for v in range(g.n) if X[v] and f[v] <= c}
+        if mode == "exact":
+            lev = {v: 0 for v in R}
+        else:
+            k, _, _, _ = oracle.sampled_lists(g, h, r, M, X)
+            lev = {v: int(k[v]) for v in R}
+        assert R == sorted(R, key=lambda v: (int(f[v]), lev[v], v))
+        assert all(core[v] == c for v in R)
+    # every core level set is a suffix
+    pos = np.empty(g.n, np.int64)
+    pos[order] = np.arange(g.n)
+    for K in np.unique(core):
+        F = np.nonzero(core >= K)[0]
+        assert pos[F].min() == g.n - F.size
+
+
+def test_dense_suffix_exact_counts_h_pairs():
+    # R of every suffix = 2 |E_h(S)| by brute-force pair counting (Sec. 6 identity)
+    g = gg.barabasi_albert(40, 2, seed=1)
+    adj = brute.adjacency(g)
+    for h in (2, 3):
+        order, _, _ = oracle.bulk_order(g, h)
+        res = oracle.dense_suffix(g, order, h)
+        for i in range(g.n):
+            S = set(order[i:].tolist())
+            assert res["R"][i] == 2 * brute.h_pairs(adj, h, S)
+        best = max(range(g.n), key=lambda i: (Fraction(int(res["R"][i]), g.n - i), i))
+        assert res["best"] == best and res["size"] == g.n - best
+
+
+def test_dense_suffix_sampled_sums_the_estimate():
+    # R of every suffix = sum of Def. est over it (estimate_all, pinned above);
+    # M >= n reduces it to the exact count; suffixes include every core level,
+    # so the best suffix is at least as dense as the best core level
+    g = gg.chung_lu(150, 600, 2.2, seed=2)
+    h = 2
+    r0, r1 = oracle.ranks(g.n, 4, 0), oracle.ranks(g.n, 4, 1)
+    order, core, _ = oracle.bulk_order(g, h, "sampled", r0, 5)
+    res = oracle.dense_suffix(g, order, h, "sampled", r1, 7)
+    for i in (0, 1, 17, 60, 149):
+        S = np.zeros(g.n, np.uint8)
+        S[order[i:]] = 1
+        assert res["R"][i] == int(oracle.estimate_all(g, h, r1, 7, S)[S == 1].sum())
+    ex = oracle.dense_suffix(g, order, h, "exact")
+    big = oracle.dense_suffix(g, order, h, "sampled", r1, g.n)
+    assert np.array_equal(ex["R"], big["R"])
+    lvl = oracle.dense(g, core, h, "sampled", r1, 7)
+    assert Fraction(res["best_R"], res["size"]) >= Fraction(lvl["R"], lvl["size"])
