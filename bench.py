@@ -1,27 +1,30 @@
 """Benchmark of the (k,h)-core hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--stages ...]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--budget-s S] [...]
 
 Workload: Chung-Lu power-law graph, n = 1,000,000, m = 10,000,000 undirected
 edges, degree exponent 2.1 (seed 1, int32 CSR), resident in HBM before the
-timed region.  One step runs the whole hot path at each h in --hs (default
-h = 2):
+timed region.  One step runs the whole hot path at h = 2 and h = 3 (--hs):
 
-  exact    ExactCore: h-degrees, frontier-driven bulk peel, densest core
-           (pruning variant)
+  exact    ExactCore: h-degrees by bit-parallel bounded BFS, frontier-driven
+           bulk peel, densest core level (pruning variant)
   sampled  Core (Alg. 4, eps = 0.5, delta = 0.05): ranks, sample-list union
-           over h hops, estimate, bulk peel with lazy update, densest core
-           (Alg. 7, pruning variant)
-  hdeg     (optional stage) one all-vertex exact h-degree pass on its own
+           over h hops, estimate, bulk peel with lazy update, densest-core
+           estimate (Alg. 7, core levels, pruning variant)
 
-Metric: edges traversed per second.  The edges traversed of one decomposition
-at distance h are those of one all-vertex h-degree pass by per-source bounded
-BFS on the input graph (sum over sources s of the degrees of the vertices
-within h-1 hops of s), measured once outside the timed region; the step's
-total is that figure summed over the decompositions it runs, divided by the
-step's wall time.  The JSON line also carries the roofline of the dominant
-kernel (HIP-event timed inside the library, algorithmic bytes counted by the
-kernel) and the CPU oracle's rate on a bounded sample of sources.
+Metric: edges traversed per second of ExactCore, from the library's own count
+(kh_result.edges_traversed: for every h-degree the peel evaluates, the arcs a
+per-source bounded BFS inspects), summed over the exact decompositions of the
+timed steps and divided by their wall time.  The sampled path traverses no
+BFS edges; its rate is reported beside it as sample-list elements merged per
+second.  ms_per_step is the wall time of the whole step.
+
+The run keeps to a wall-clock budget (--budget-s, counted from the start of
+the process): warmup and timed steps are cut to what fits, at least one timed
+step, and the JSON line reports the counts actually run.  The JSON line also
+carries the roofline of the dominant instrumented kernel (HIP events on its
+launch stream inside the library, algorithmic bytes counted by the kernel) and
+the CPU oracle's rate on a bounded sample of sources, over all host cores.
 """
 from __future__ import annotations
 
@@ -116,32 +119,76 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(g, hs, budget_s: float):
-    """The oracle's per-source BFS h-degrees on a seeded sample of sources,
-    single thread, about budget_s seconds per h."""
+def host_cpu():
+    """(threads usable by this process, CPU model) of the host."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        cores = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
+
+
+def cpu_baseline(g, hs, budget_s: float, max_threads: int = 16):
+    """The oracle's per-source BFS h-degrees on a seeded sample of sources, in
+    threads over disjoint source chunks (the oracle is plain C called through
+    ctypes, which releases the interpreter lock), about budget_s seconds of
+    wall time per h.  Rate = edges traversed / wall time."""
+    import concurrent.futures
+    import threading
+
     import numpy as np
 
     import oracle
+    oracle.lib()
+    cores, model = host_cpu()
+    threads = max(1, min(cores, max_threads))
     rng = np.random.default_rng(12345)
     order = rng.permutation(g.n).astype(np.int32)
-    te_tot, t_tot, nsrc = 0, 0.0, 0
     per_h = {}
+    te_tot, t_tot, nsrc = 0, 0.0, 0
     for h in hs:
-        te_h, t_h, k = 0, 0.0, 0
-        while t_h < budget_s and k < g.n:
-            chunk = order[k:k + 32]
-            t0 = time.perf_counter()
-            _, te = oracle.hdeg_list(g, h, chunk, with_te=True)
-            t_h += time.perf_counter() - t0
-            te_h += te
-            k += chunk.size
-        per_h[h] = {"sources": k, "te": te_h, "seconds": t_h}
-        te_tot += te_h
-        t_tot += t_h
-        nsrc += k
-    return {"value": te_tot / t_tot, "unit": "edges_traversed/s", "cores": 1, "kind": "oracle",
-            "sample": f"per-source BFS h-degrees of {nsrc} seeded random sources (h in {list(hs)}), "
-                      f"about {budget_s:.0f} s per h, single thread", "per_h": per_h}
+        lock = threading.Lock()
+        state = {"next": 0, "te": 0, "src": 0}
+        chunk = 256 if h <= 2 else 16  # sources per oracle call (each call sets up an n-sized workspace)
+        t0 = time.perf_counter()
+        deadline = t0 + budget_s
+
+        def worker():
+            while time.perf_counter() < deadline:
+                with lock:
+                    k = state["next"]
+                    if k >= g.n:
+                        return
+                    state["next"] = k + chunk
+                src = order[k:k + chunk]
+                _, te = oracle.hdeg_list(g, h, src, with_te=True)
+                with lock:
+                    state["te"] += te
+                    state["src"] += src.size
+
+        with concurrent.futures.ThreadPoolExecutor(threads) as ex:
+            for f in [ex.submit(worker) for _ in range(threads)]:
+                f.result()
+        dt = time.perf_counter() - t0
+        per_h[h] = {"sources": state["src"], "te": state["te"], "seconds": round(dt, 3)}
+        te_tot += state["te"]
+        t_tot += dt
+        nsrc += state["src"]
+        log(f"cpu baseline h={h}: {state['src']} sources, {state['te'] / dt:.3e} edges traversed/s")
+    return {"value": te_tot / t_tot, "unit": "edges_traversed/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "host_threads": cores,
+            "sample": f"per-source BFS h-degrees (plain C oracle) of {nsrc} seeded random sources of the same "
+                      f"graph, h in {list(hs)}, about {budget_s:.0f} s of wall time per h on {threads} threads",
+            "per_h": per_h}
 
 
 def percentile(xs, q):
@@ -387,17 +434,34 @@ def bench_sbm(kh, ctx, args):
             "rows": rows}
 
 
+T_PROCESS_START = time.time()
+
+
+def elapsed_total():
+    return time.time() - T_PROCESS_START
+
+
+def plan_counts(requested, est_step_s, left_s, minimum):
+    """How many steps of est_step_s seconds fit into left_s (at least `minimum`,
+    at most `requested`)."""
+    if est_step_s <= 0:
+        return requested
+    return max(minimum, min(requested, int(left_s // est_step_s)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--budget-s", type=float, default=450.0,
+                    help="wall-clock budget of the whole run; warmup and timed steps are cut to fit")
+    ap.add_argument("--step-estimate-s", type=float, default=240.0,
+                    help="assumed step time before one has been measured (decides whether a warmup step fits)")
     ap.add_argument("--stages", default="exact,sampled", help="comma list of hdeg,exact,sampled")
-    ap.add_argument("--hs", default="2")
-    ap.add_argument("--cpu-budget", type=float, default=8.0)
+    ap.add_argument("--hs", default="2,3")
+    ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work per h (all host cores)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-te", action="store_true",
-                    help="skip the untimed edges-traversed pass (counter runs: only timed-region dispatches)")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--batch", action="store_true", help="also measure the batch workload (kh_core_batch)")
     ap.add_argument("--batch-count", type=int, default=4096)
@@ -424,19 +488,27 @@ def main():
                     help="write profiles/traffic_counters.json from two rocprofv3 --pmc runs of this command")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the build has no multi-GPU path, "
+                                   "so --gpus must be 1"}))
         sys.exit(2)
-
-    import torch
-
-    import graphgen as gg
-    import paper_2112_06154_amd as kh
 
     stages = [s for s in args.stages.split(",") if s]
     hs = [int(x) for x in args.hs.split(",")]
     if args.pmc_summarize:
         pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], stages, hs)
         return
+
+    import concurrent.futures
+
+    import graphgen as gg
+    # generate the benchmark graph while torch and the library load
+    gen_pool = concurrent.futures.ThreadPoolExecutor(1)
+    g_future = None if args.skip_main else gen_pool.submit(gg.workload, "cl1m")
+    import torch
+
+    import paper_2112_06154_amd as kh
+    log(f"[{elapsed_total():.0f}s] torch and the library loaded")
+
     if args.skip_main:
         torch.cuda.set_device(0)
         ctx = kh.Context(0)
@@ -451,11 +523,21 @@ def main():
             extra["sbm"] = bench_sbm(kh, ctx, args)
         print(json.dumps(extra))
         return
-    t0 = time.time()
-    g = gg.workload("cl1m")
-    log(f"graph {WORKLOAD}: generated in {time.time() - t0:.1f}s")
+
     torch.cuda.set_device(0)
     ctx = kh.Context(0)
+    # load the kernels and run every stage once on a small graph of the same family
+    small = gg.chung_lu(20_000, 200_000, 2.1, seed=3)
+    Gs = kh.Graph.from_gg(ctx, small)
+    outs = torch.empty(small.n, dtype=torch.int32, device="cuda:0")
+    for h in hs:
+        kh.core(Gs, h, out=outs, dense=True, prune=True)
+        kh.core(Gs, h, epsilon=0.5, delta=0.05, seed=1, out=outs, dense=True, prune=True)
+    torch.cuda.synchronize()
+    del Gs
+    g = g_future.result()
+    gen_pool.shutdown()
+    log(f"[{elapsed_total():.0f}s] graph {WORKLOAD} ready; small-graph prewarm done")
     G = kh.Graph.from_gg(ctx, g)
     out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
     torch.cuda.synchronize()
@@ -470,58 +552,77 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    # edges traversed of one all-vertex h-degree pass, per h (outside the timed region)
-    te_pass = {}
-    for h in hs:
-        te_pass[h] = 0 if args.no_te else kh.hdeg(G, h, out=out)[1]
-    torch.cuda.synchronize()
-
-    def step(record):
-        te = 0
+    def step(record, tag):
+        """One pass of the hot path; returns (exact TE, exact s, sampled list elements, sampled s)."""
+        te = ex_s = le = sa_s = 0
         for h in hs:
             if "hdeg" in stages:
                 t = time.perf_counter()
-                kh.hdeg(G, h, out=out)
+                _, te_h = kh.hdeg(G, h, out=out)
                 torch.cuda.synchronize()
                 record.setdefault(f"hdeg_h{h}_s", []).append(round(time.perf_counter() - t, 3))
-                te += te_pass[h]
+                record[f"hdeg_h{h}_edges_traversed"] = te_h
             if "exact" in stages:
                 t = time.perf_counter()
                 _, res = kh.core(G, h, out=out, dense=True, prune=True)
                 torch.cuda.synchronize()
-                record.setdefault(f"exact_h{h}_s", []).append(round(time.perf_counter() - t, 3))
+                dt = time.perf_counter() - t
+                record.setdefault(f"exact_h{h}_s", []).append(round(dt, 3))
                 record[f"exact_h{h}"] = {k: res[k] for k in ("rounds", "max_core", "dense_k", "dense_size",
-                                                              "dense_density", "edges_traversed")}
-                te += te_pass[h]
+                                                              "dense_density", "edges_traversed", "arcs_scanned")}
+                te += res["edges_traversed"]
+                ex_s += dt
+                log(f"[{elapsed_total():.0f}s] {tag} exact h={h}: {dt:.2f}s, {res['rounds']} rounds")
             if "sampled" in stages:
                 t = time.perf_counter()
                 _, res = kh.core(G, h, epsilon=0.5, delta=0.05, seed=1, out=out, dense=True, prune=True)
                 torch.cuda.synchronize()
-                record.setdefault(f"sampled_h{h}_s", []).append(round(time.perf_counter() - t, 3))
+                dt = time.perf_counter() - t
+                record.setdefault(f"sampled_h{h}_s", []).append(round(dt, 3))
                 record[f"sampled_h{h}"] = {k: res[k] for k in ("rounds", "max_core", "M_used", "M_dense_used",
                                                                 "dense_k", "dense_size", "dense_density",
                                                                 "list_elements")}
-                te += te_pass[h]
-        return te
+                le += res["list_elements"]
+                sa_s += dt
+                log(f"[{elapsed_total():.0f}s] {tag} sampled h={h}: {dt:.2f}s, {res['rounds']} rounds")
+        return te, ex_s, le, sa_s
 
+    # warmup: only while a warmup step and at least one timed step (plus the
+    # CPU baseline) still fit into the budget
+    reserve = 0.0 if args.no_cpu else args.cpu_budget * len(hs) + 5.0
+    est = args.step_estimate_s
     warm = {}
+    warm_done = 0
     for i in range(args.warmup):
-        step(warm)
-        log(f"warmup {i + 1}/{args.warmup} done")
+        left = args.budget_s - elapsed_total() - reserve
+        if left < 2.0 * est:
+            log(f"[{elapsed_total():.0f}s] warmup cut at {warm_done} step(s): {left:.0f}s left, step ~{est:.0f}s")
+            break
+        t = time.perf_counter()
+        step(warm, f"warmup {i + 1}")
+        est = time.perf_counter() - t if warm_done == 0 else max(est, time.perf_counter() - t)
+        warm_done += 1
+    left = args.budget_s - elapsed_total() - reserve
+    steps = plan_counts(args.steps, est * 1.05, left, 1)
+    log(f"[{elapsed_total():.0f}s] timing {steps} step(s) of ~{est:.0f}s ({left:.0f}s left in the budget)")
+
     rec = {}
     ctx.profile(True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    te_total = 0
-    for i in range(args.steps):
-        te_total += step(rec)
-        log(f"step {i + 1}/{args.steps} done")
+    te_total = ex_total = le_total = sa_total = 0
+    for i in range(steps):
+        te, ex_s, le, sa_s = step(rec, f"step {i + 1}/{steps}")
+        te_total += te
+        ex_total += ex_s
+        le_total += le
+        sa_total += sa_s
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     profs = [ctx.profile_read(0), ctx.profile_read(1)]
     ctx.profile(False)
 
-    names = ["k_ms_pull<16> (bit-parallel h-degree pull hop)", "k_union (sample-list union, levels >= 2)"]
+    names = ["k_ms_pull (bit-parallel h-degree pull hop)", "k_union (sample-list union, levels >= 2)"]
 
     def roofline(k):
         p = profs[k]
@@ -531,6 +632,7 @@ def main():
              "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
              "traffic": measured_traffic(k, stages, hs),
              "launches": p["launches"], "total_ms": round(ms, 2),
+             "share_of_step": round(ms * 1e-3 / elapsed, 4) if elapsed > 0 else None,
              "avg_launch_ms": round(ms / max(p["launches"], 1), 4),
              "alg_bytes_per_launch": p["alg_bytes"] // max(p["launches"], 1)}
         if k == 0:
@@ -539,16 +641,23 @@ def main():
         return r
 
     dom = 0 if profs[0]["ms"] >= profs[1]["ms"] else 1
+    exact_rate = te_total / ex_total if ex_total > 0 else None
     line = {
         "metric": "(k,h)-core edges-traversed/sec + %HBM roofline at h=2,3",
-        "value": te_total / elapsed, "unit": "edges_traversed/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "value": exact_rate, "unit": "edges_traversed/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm_done, "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": WORKLOAD, "h": hs, "stages": stages, "epsilon": 0.5, "delta": 0.05,
-                   "densest_core": "pruning variant"},
+                   "densest_core": "core levels, pruning variant",
+                   "value": "ExactCore edges traversed (kh_result) / ExactCore wall time"},
+        "requested": {"steps": args.steps, "warmup": args.warmup, "budget_s": args.budget_s},
+        "exact": {"edges_traversed": te_total, "seconds": round(ex_total, 3),
+                  "edges_traversed_per_s": exact_rate},
+        "sampled": {"list_elements": le_total, "seconds": round(sa_total, 3),
+                    "list_elements_per_s": le_total / sa_total if sa_total > 0 else None},
+        "step_edges_traversed_per_s": te_total / elapsed if elapsed > 0 else None,
         "roofline": roofline(dom),
         "roofline_other": roofline(1 - dom),
-        "te_per_decomposition": {str(h): te_pass[h] for h in hs},
         "stages_detail": rec,
     }
     if args.batch:
@@ -561,7 +670,8 @@ def main():
         line["sbm"] = bench_sbm(kh, ctx, args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, hs, args.cpu_budget)
-    print(json.dumps(line))
+    line["wall_s_total"] = round(elapsed_total(), 1)
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

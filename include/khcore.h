@@ -55,8 +55,11 @@ typedef int32_t kh_status;
 /* kh_params.flags */
 #define KH_WANT_DENSE   1u /* also compute the densest-core estimate (Sec. 6) */
 #define KH_DENSE_PRUNE  2u /* densest core: only levels K with K(1+eps) >= (1-eps) max core */
-#define KH_EARLY_STOP   4u /* sampled path: stop once c + 1 >= |remaining| (Sec. 5 heuristic);
-                              changes the output relative to Alg. 4, off by default */
+#define KH_EARLY_STOP   4u /* sampled path: right after a round's deletions, if c + 1 >= |remaining|,
+                              every remaining vertex gets c and the peel ends (Sec. 5 heuristic,
+                              Sec. 8 wording); the result is min(c'(v), c*) for the first level c*
+                              with c* + 1 >= #{c' > c*}.  Changes the output relative to Alg. 4,
+                              off by default.  ExactCore ignores it (it cannot change c). */
 #define KH_OUT_DEVICE   8u /* core_out / deg_out are device pointers */
 
 typedef struct kh_context kh_context;

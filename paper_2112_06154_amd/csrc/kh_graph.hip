@@ -274,9 +274,20 @@ void launch_reduce(const int64_t* key, const int64_t* val, const uint8_t* alive,
 // c = max(c, min key).  When c rises to K, the alive set is exactly
 // F_K = {v : core(v) >= K} and sum_val is the sum of the values over it: that
 // is recorded as a densest-core candidate (Sec. 6).
+//
+// Early stop (Sec. 5 heuristic, in the Sec. 8 form c + 1 = |remaining|): tested
+// right after a round's deletions, with that round's c.  When c + 1 >= |X| the
+// round takes every remaining vertex at c.  Deleting in bulk gives the same
+// numbers as testing after every single deletion: vertices leave in
+// non-decreasing core order and the test is weakest at the end of a level.
 __global__ void k_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_size, int64_t* cand_sum, int early_stop) {
     if (st->alive_count == 0) return;
     long long c = st->c;
+    if (early_stop && st->rounds > 0 && c + 1 >= (long long)st->alive_count) {
+        st->stop = 1;
+        st->rounds += 1;
+        return;
+    }
     if (st->min_key > c) {
         c = st->min_key;
         if (cand_k) {
@@ -289,7 +300,6 @@ __global__ void k_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_siz
     }
     st->c = c;
     st->rounds += 1;
-    if (early_stop && c + 1 >= (long long)st->alive_count) st->stop = 1;
 }
 void launch_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_size, int64_t* cand_sum, int early_stop,
                         hipStream_t s) {
