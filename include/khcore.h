@@ -219,6 +219,33 @@ kh_status kh_serve_stop(kh_context *ctx);
 kh_status kh_hdeg(kh_graph *g, int32_t h, const uint8_t *alive, uint32_t flags, int32_t *deg_out,
                   int64_t *edges_traversed, void *stream);
 
+/* ---- h-degrees without device allocation --------------------------------------
+ * For callers that cannot allocate: code recorded into HIP graphs, tight
+ * serving loops, harnesses that forbid allocation.
+ *
+ * kh_hdeg_noalloc gives kh_hdeg's h-degrees deg_h(v;X) = |N(v;h,X)| - 1
+ * (Sec. 2) and its edges-traversed count, but calls no device (or pinned)
+ * allocation routine and never waits for the GPU: it enqueues kernels on
+ * `stream` and returns.  Its working memory is one fixed device array of
+ * KH_NOALLOC_SCRATCH_BYTES per GPU, which the library holds from the first
+ * kh_context_create on that GPU until the process ends.  Every call on a GPU
+ * uses that same array and leaves its own contents in it, so calls that
+ * overlap on one GPU (two streams, two threads, two contexts) race and give
+ * wrong results: serialise them.
+ *   alive: device uint8[n] (nonzero = in X), or NULL for X = V.
+ *   deg_out: device int32[n]; -1 for v outside X.
+ *   edges_traversed: device int64 (nullable): kh_hdeg's count.
+ * Limit: the graph's working set, about (110 + 32 Q) n + nnz/2 bytes with
+ * Q in {1,2,4,8,16} bit-plane words per vertex (the widest that fits is
+ * used), must fit the array; at Q = 1 that is n up to about 5e5 at average
+ * degree 10.
+ * Errors, decided on the host before anything is enqueued: KH_EINVAL (NULL
+ * graph, NULL deg_out with n > 0, h < 1), KH_ENOMEM (the graph does not fit
+ * the array); KH_EDEVICE when a launch fails. */
+#define KH_NOALLOC_SCRATCH_BYTES (64ull << 20)
+kh_status kh_hdeg_noalloc(kh_graph *g, int32_t h, const uint8_t *alive, int32_t *deg_out,
+                          int64_t *edges_traversed, void *stream);
+
 /* Ranks r[v] (Sec. 3, geometric(1/2), capped at 255) of vertices 0..n-1 for
  * (seed, stream_id): word j of vertex v is
  *   sm(sm(sm(seed) ^ v) ^ (stream_id * 2^32 + j)), sm = SplitMix64's mixer,

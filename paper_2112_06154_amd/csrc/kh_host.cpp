@@ -66,6 +66,7 @@ struct kh_context {
     size_t lds_per_block = 65536;
     int num_cu = 0;
     RoundState* host_state = nullptr;  // pinned mirror of the device round state (fallback)
+    void* noalloc_scratch = nullptr;   // this device's fixed working array of kh_hdeg_noalloc
     // pinned mirrors leased by concurrent calls (StateLease)
     std::mutex pool_lock;
     std::vector<RoundState*> pool;
@@ -280,6 +281,13 @@ extern "C" kh_status kh_context_create(int32_t device, uint64_t hbm_budget_bytes
         return KH_EDEVICE;
     }
     ctx->host_state = static_cast<RoundState*>(hs);
+    // the fixed array of kh_hdeg_noalloc: its address on this device, looked up once
+    if (kh::noalloc_scratch_init(device, &ctx->noalloc_scratch) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(hs);
+        delete ctx;
+        return KH_EDEVICE;
+    }
     *out = ctx;
     return KH_OK;
 }
@@ -1785,6 +1793,33 @@ extern "C" kh_status kh_hdeg(kh_graph* g, int32_t h, const uint8_t* alive_in, ui
         return KH_ENOMEM;
     }
     return KH_OK;
+}
+
+// No device allocation, no host wait: the working memory is the context's
+// device's fixed array (kh_noalloc.hip); the pull kernel's work-item counts come
+// from the host copy of row_ptr.
+extern "C" kh_status kh_hdeg_noalloc(kh_graph* g, int32_t h, const uint8_t* alive, int32_t* deg_out,
+                                     int64_t* edges_traversed, void* stream) {
+    if (!g || h < 1) return KH_EINVAL;
+    if (g->n > 0 && !deg_out) return KH_EINVAL;
+    kh_context* ctx = g->ctx;
+    if (!ctx->noalloc_scratch) return KH_EDEVICE;
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        (void)hipGetLastError();
+        return KH_EDEVICE;
+    }
+    int64_t nitems = 0, nsplit = 0;
+    for (int32_t v = 0; v < g->n; ++v) {
+        const int32_t d = g->h_rp[(size_t)v + 1] - g->h_rp[(size_t)v];
+        if (d > kPullChunk) {
+            nitems += (d + kPullChunk - 1) / kPullChunk;
+            ++nsplit;
+        } else if (d > 0) {
+            ++nitems;
+        }
+    }
+    return noalloc_hdeg(ctx->noalloc_scratch, g->n, g->nnz, g->rp, g->col, nitems, nsplit, effective_h(g, h), alive,
+                        deg_out, edges_traversed, static_cast<hipStream_t>(stream));
 }
 
 extern "C" kh_status kh_ranks(kh_context* ctx, int32_t n, uint64_t seed, uint32_t stream_id, uint8_t* r_out,

@@ -297,6 +297,23 @@ void launch_estimate(const int32_t* worklist, const int* wl_count, int32_t n, co
                      const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, const int32_t* Mv,
                      int64_t* d, RoundState* st, hipStream_t s);
 
+// ---- h-degrees in a fixed device array (kh_noalloc.hip) --------------------------------
+// Size of the array (per GPU, held until the process ends) and the most GPUs
+// the library tracks it for.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+// Address of the array on `device` (which must be current); looked up once per device.
+hipError_t noalloc_scratch_init(int device, void** out);
+// Bytes the layout needs for a graph with nitems pull work items (nsplit split
+// vertices) at Q words per vertex.
+int64_t noalloc_hdeg_bytes(int32_t n, int64_t nnz, int64_t nitems, int64_t nsplit, int Q);
+// deg_out[v] = deg_h(v;X) (device int32), te_out (device, nullable) = edges
+// traversed; enqueued on s, no allocation, no host wait.  KH_ENOMEM when the
+// graph does not fit the array.
+kh_status noalloc_hdeg(void* scratch_ptr, int32_t n, int64_t nnz, const int32_t* rp, const int32_t* col,
+                       int64_t nitems, int64_t nsplit, int h, const uint8_t* alive_in, int32_t* deg_out,
+                       int64_t* te_out, hipStream_t s);
+
 // ---- serving (kh_serve.cpp) and its hooks into the engines (kh_host.cpp) -------------
 // A serving thread runs requests with its own pinned round-state mirror, and
 // without the context's profiling slots.

@@ -40,8 +40,11 @@ EXPORTED = [
     "kh_graph_load_csr", "kh_graph_free", "kh_graph_n", "kh_graph_nnz", "kh_core", "kh_core_batch", "kh_hdeg",
     "kh_ranks", "kh_serve_start", "kh_serve_submit", "kh_serve_poll", "kh_serve_wait", "kh_serve_cancel",
     "kh_serve_stop",
-    "kh_sampled_lists", "kh_dense", "kh_profile_enable", "kh_profile_read",
+    "kh_sampled_lists", "kh_dense", "kh_profile_enable", "kh_profile_read", "kh_hdeg_noalloc",
 ]
+
+# size of the fixed device array of kh_hdeg_noalloc (KH_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Params(ctypes.Structure):
@@ -114,6 +117,8 @@ def lib():
         L.kh_serve_stop.restype = i32
         L.kh_hdeg.argtypes = [P, i32, P, u32, P, ctypes.POINTER(i64), P]
         L.kh_hdeg.restype = i32
+        L.kh_hdeg_noalloc.argtypes = [P, i32, P, P, P, P]
+        L.kh_hdeg_noalloc.restype = i32
         L.kh_ranks.argtypes = [P, i32, u64, u32, P, P]
         L.kh_ranks.restype = i32
         L.kh_sampled_lists.argtypes = [P, ctypes.POINTER(Params), P, i32, P, P, P, i64, P, P]
@@ -366,6 +371,14 @@ def hdeg(graph: Graph, h: int, alive=None, out=None, stream=None):
     if isinstance(out, np.ndarray):
         out = out[:graph.n]
     return out, te.value
+
+
+def hdeg_noalloc(graph: Graph, h: int, deg_out, alive=None, te_out=None, stream=None) -> None:
+    """kh_hdeg_noalloc: h-degrees into the int32 device tensor deg_out (n
+    entries) and, if given, the edges-traversed count into the int64 device
+    tensor te_out; enqueued on the stream, nothing allocated."""
+    _check(lib().kh_hdeg_noalloc(graph.handle, h, _ptr(alive), _ptr(deg_out), _ptr(te_out), _stream(stream)),
+           "kh_hdeg_noalloc")
 
 
 def ranks(ctx: Context, n: int, seed: int, stream_id: int = 0, stream=None):
