@@ -39,7 +39,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 WORKLOAD = "chung_lu n=1000000 m=10000000 gamma=2.1 seed=1"
-KERNEL_SRC = {0: "paper_2112_06154_amd/csrc/kh_msbfs.hip", 1: "paper_2112_06154_amd/csrc/kh_union.hip"}
+KERNEL_SRC = {0: "paper_2112_06154_amd/csrc/kh_msbfs.hip", 1: "paper_2112_06154_amd/csrc/kh_union.hip",
+              2: "paper_2112_06154_amd/csrc/kh_graph.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
 
 
@@ -68,7 +69,8 @@ def measured_traffic(k, stages, hs):
 # the dispatches counted as one launch of a reported kernel (the union's hubs
 # are merged by a second, wider variant inside the same timed launch)
 KERNEL_NAMES = {0: ["k_ms_pull<16>", "k_ms_pull<8>", "k_ms_pull<4>", "k_ms_pull<2>", "k_ms_pull<1>"],
-                1: ["k_union<256>", "k_union<1024>"]}
+                1: ["k_union<256>", "k_union<1024>"],
+                2: ["k_rbfs_expand", "k_rbfs_pull"]}
 # FETCH_SIZE reads 524,317 KiB for the 1 GiB read by the add kernel of
 # --copy-calib, WRITE_SIZE 1,048,576 KiB for its 1 GiB write
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
@@ -283,7 +285,7 @@ def bench_serve(kh, ctx, args):
         now = time.perf_counter() - t_start
         while i < nreq and arrivals[i] <= now:
             eps = 0.5 if modes[i] else 0.0
-            kw = dict(seed=1) if eps > 0 else {}
+            kw = dict(seed=1, lazy_init=int(hs[i]) in args.lazy_set) if eps > 0 else {}
             tk = srv.submit(Gs[picks[i]], int(hs[i]), epsilon=eps, **kw)
             pending.append((tk, i))
             i += 1
@@ -360,7 +362,8 @@ def bench_cl4m(kh, ctx, args):
     for eps in ([] if args.dev_only else [float(x) for x in args.cl4m_eps.split(",")]):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, res = kh.core(G, 3, epsilon=eps, delta=0.05, seed=1, out=core_out, dense=True, prune=True)
+        _, res = kh.core(G, 3, epsilon=eps, delta=0.05, seed=1, out=core_out, dense=True, prune=True,
+                         lazy_init=3 in args.lazy_set)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         log(f"cl4m sampled h=3 eps={eps}: {dt:.1f}s")
@@ -381,7 +384,7 @@ def bench_cl4m(kh, ctx, args):
     exv = ex.astype(np.float64)
     for eps in [float(x) for x in args.cl4m_eps.split(",")]:
         t = time.perf_counter()
-        sc, rs = kh.core(Gs, 3, epsilon=eps, delta=0.05, seed=1)
+        sc, rs = kh.core(Gs, 3, epsilon=eps, delta=0.05, seed=1, lazy_init=3 in args.lazy_set)
         ts = time.perf_counter() - t
         pos = exv > 0
         ratio = sc[pos].astype(np.float64) / exv[pos]
@@ -460,6 +463,9 @@ def main():
                     help="assumed step time before one has been measured (decides whether a warmup step fits)")
     ap.add_argument("--stages", default="exact,sampled", help="comma list of hdeg,exact,sampled")
     ap.add_argument("--hs", default="2,3")
+    ap.add_argument("--lazy-hs", default="3",
+                    help="h values at which the sampled stage uses the lazy initialisation of the top level "
+                         "(Sec. 5 heuristic; output-neutral); empty: none")
     ap.add_argument("--cpu-budget", type=float, default=10.0, help="seconds of oracle work per h (all host cores)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="also run a 1 GiB device copy (counter calibration)")
@@ -494,6 +500,8 @@ def main():
 
     stages = [s for s in args.stages.split(",") if s]
     hs = [int(x) for x in args.hs.split(",")]
+    lazy_hs = {int(x) for x in args.lazy_hs.split(",") if x}
+    args.lazy_set = lazy_hs
     if args.pmc_summarize:
         pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], stages, hs)
         return
@@ -501,6 +509,8 @@ def main():
     import concurrent.futures
 
     import graphgen as gg
+    # the library's round loops print a line every 20 s of a long decomposition
+    os.environ.setdefault("KH_HEARTBEAT", "20")
     # generate the benchmark graph while torch and the library load
     gen_pool = concurrent.futures.ThreadPoolExecutor(1)
     g_future = None if args.skip_main else gen_pool.submit(gg.workload, "cl1m")
@@ -532,7 +542,7 @@ def main():
     outs = torch.empty(small.n, dtype=torch.int32, device="cuda:0")
     for h in hs:
         kh.core(Gs, h, out=outs, dense=True, prune=True)
-        kh.core(Gs, h, epsilon=0.5, delta=0.05, seed=1, out=outs, dense=True, prune=True)
+        kh.core(Gs, h, epsilon=0.5, delta=0.05, seed=1, out=outs, dense=True, prune=True, lazy_init=h in lazy_hs)
     torch.cuda.synchronize()
     del Gs
     g = g_future.result()
@@ -575,7 +585,8 @@ def main():
                 log(f"[{elapsed_total():.0f}s] {tag} exact h={h}: {dt:.2f}s, {res['rounds']} rounds")
             if "sampled" in stages:
                 t = time.perf_counter()
-                _, res = kh.core(G, h, epsilon=0.5, delta=0.05, seed=1, out=out, dense=True, prune=True)
+                _, res = kh.core(G, h, epsilon=0.5, delta=0.05, seed=1, out=out, dense=True, prune=True,
+                                 lazy_init=h in lazy_hs)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t
                 record.setdefault(f"sampled_h{h}_s", []).append(round(dt, 3))
@@ -619,10 +630,11 @@ def main():
         sa_total += sa_s
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    profs = [ctx.profile_read(0), ctx.profile_read(1)]
+    profs = [ctx.profile_read(0), ctx.profile_read(1), ctx.profile_read(2)]
     ctx.profile(False)
 
-    names = ["k_ms_pull (bit-parallel h-degree pull hop)", "k_union (sample-list union, levels >= 2)"]
+    names = ["k_ms_pull (bit-parallel h-degree pull hop)", "k_union (sample-list union, levels >= 2)",
+             "k_rbfs_expand / k_rbfs_pull (exact peel: one hop of the deleted set's mask BFS)"]
 
     def roofline(k):
         p = profs[k]
@@ -640,7 +652,8 @@ def main():
             r["gather_gbs"] = round((p["gather_bytes"] / (ms * 1e-3)) / 1e9, 2) if ms > 0 else 0.0
         return r
 
-    dom = 0 if profs[0]["ms"] >= profs[1]["ms"] else 1
+    order = sorted(range(len(profs)), key=lambda k: -profs[k]["ms"])
+    dom = order[0]
     exact_rate = te_total / ex_total if ex_total > 0 else None
     line = {
         "metric": "(k,h)-core edges-traversed/sec + %HBM roofline at h=2,3",
@@ -648,7 +661,7 @@ def main():
         "warmup": warm_done, "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": WORKLOAD, "h": hs, "stages": stages, "epsilon": 0.5, "delta": 0.05,
-                   "densest_core": "core levels, pruning variant",
+                   "densest_core": "core levels, pruning variant", "lazy_init_at_h": sorted(lazy_hs),
                    "value": "ExactCore edges traversed (kh_result) / ExactCore wall time"},
         "requested": {"steps": args.steps, "warmup": args.warmup, "budget_s": args.budget_s},
         "exact": {"edges_traversed": te_total, "seconds": round(ex_total, 3),
@@ -657,7 +670,7 @@ def main():
                     "list_elements_per_s": le_total / sa_total if sa_total > 0 else None},
         "step_edges_traversed_per_s": te_total / elapsed if elapsed > 0 else None,
         "roofline": roofline(dom),
-        "roofline_other": roofline(1 - dom),
+        "roofline_other": [roofline(k) for k in order[1:]],
         "stages_detail": rec,
     }
     if args.batch:

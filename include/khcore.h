@@ -61,6 +61,19 @@ typedef int32_t kh_status;
                               with c* + 1 >= #{c' > c*}.  Changes the output relative to Alg. 4,
                               off by default.  ExactCore ignores it (it cannot change c). */
 #define KH_OUT_DEVICE   8u /* core_out / deg_out are device pointers */
+#define KH_LAZY_INIT   32u /* sampled path: build B[v,h] only once a lower bound on v's estimate
+                              from its neighbours' level h-1 lists (Prop. monotone) no longer keeps
+                              v above the running maximum (Sec. 5, first heuristic).  The output is
+                              unchanged; h >= 2 (ignored for h = 1). */
+#define KH_DENSE_FULL  16u /* with KH_WANT_DENSE: Alg. 7 over every suffix of the deletion order
+                              (the peel's bulk rounds in sequence; inside a round by the key at
+                              deletion -- the estimate or deg_h -- then k[v,h], then id) instead of
+                              the core levels only; every core level is such a suffix.  With
+                              KH_DENSE_PRUNE the suffixes start inside {v : c(v) >= gamma k'}.
+                              dense_k is then the smallest core number in the chosen set.  One
+                              replay round per vertex: meant for graphs up to ~1e5 vertices.
+                              kh_core only (KH_ENOTIMPL for kh_core_batch, kh_dense, and with
+                              KH_EARLY_STOP). */
 
 typedef struct kh_context kh_context;
 typedef struct kh_graph kh_graph;
@@ -73,7 +86,8 @@ typedef struct kh_params {
     uint64_t seed;         /* seed of the rank stream (ranks are geometric(1/2), Sec. 3) */
     int32_t  M_override;   /* > 0: use this integer M instead of Eq. (buffer) for Core */
     int32_t  M_dense_override; /* > 0: same for the densest-core pass (Alg. 7) */
-    uint32_t flags;        /* KH_WANT_DENSE | KH_DENSE_PRUNE | KH_EARLY_STOP | KH_OUT_DEVICE */
+    uint32_t flags;        /* KH_WANT_DENSE | KH_DENSE_PRUNE | KH_EARLY_STOP | KH_OUT_DEVICE | KH_DENSE_FULL
+                              | KH_LAZY_INIT */
 } kh_params;
 
 typedef struct kh_result {
@@ -81,8 +95,9 @@ typedef struct kh_result {
     int32_t M_dense_used;    /* integer M of the densest-core pass (0 if exact or not run) */
     int32_t rounds;          /* bulk peeling rounds */
     int32_t max_core;        /* largest core number */
-    int64_t dense_k;         /* densest core level K* (-1 if not computed) */
-    int64_t dense_size;      /* |F_K*|, F_K = {v : core[v] >= K} */
+    int64_t dense_k;         /* densest core level K* (-1 if not computed); with KH_DENSE_FULL the
+                                smallest core number in the chosen suffix */
+    int64_t dense_size;      /* |F_K*|, F_K = {v : core[v] >= K} (KH_DENSE_FULL: the suffix's size) */
     int64_t dense_R;         /* sum over F_K* of deg_h (exact) or of the estimate (sampled) */
     double  dense_density;   /* dense_R / (2 dense_size): the (estimated) h-density |E_h|/|F| */
     int64_t edges_traversed; /* exact path: sum over processed sources s of the alive degrees of
@@ -110,7 +125,9 @@ kh_status kh_validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const 
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
  * memory the library may hold for this context (0 = no cap beyond the GPU's).
- * KH_EDEVICE when the device is missing. */
+ * Device blocks that a call released are kept by the context for reuse by
+ * later calls (at most a quarter of the budget, or of the device's memory)
+ * until kh_context_destroy.  KH_EDEVICE when the device is missing. */
 kh_status kh_context_create(int32_t device, uint64_t hbm_budget_bytes, kh_context **out);
 void kh_context_destroy(kh_context *ctx);
 
@@ -165,8 +182,10 @@ kh_status kh_core_batch(kh_context *ctx, int32_t count, kh_graph *const *graphs,
  * context.  Worker threads, each with its own HIP stream, admit requests in
  * arrival order as soon as a worker is free and the request's device-memory
  * estimate fits next to the running ones; queued requests with identical
- * kh_params join an admitted one in a single kh_core_batch call (continuous
- * batching), so requests that arrive while others run overlap on the GPU.
+ * kh_params and a graph within a factor 4 of its size join an admitted one in a
+ * single kh_core_batch call (continuous batching), so requests that arrive
+ * while others run overlap on the GPU and no request waits for a much larger
+ * one packed with it.
  * Each request's core_out and result equal those of kh_core on its graph
  * alone.  The graph and core_out must stay valid until the request's result
  * has been collected (kh_serve_poll / kh_serve_wait return other than
@@ -178,7 +197,8 @@ kh_status kh_core_batch(kh_context *ctx, int32_t count, kh_graph *const *graphs,
 /* Start the serving loop of ctx: `workers` threads (0: 4), admission within
  * hbm_budget_bytes (0: 80% of the device memory free now), at most queue_cap
  * waiting requests (0: 65536), packed batches of at most batch_vertices
- * vertices (0: 2^20; a packed batch finishes all its requests together).
+ * vertices (0: 2^20; a packed batch finishes its requests together, which is why it only
+ * packs graphs of similar size).
  * KH_EBUSY if ctx already serves.  kh_serve_submit starts the loop with the
  * defaults when needed. */
 kh_status kh_serve_start(kh_context *ctx, int32_t workers, uint64_t hbm_budget_bytes, int32_t queue_cap,
@@ -239,6 +259,8 @@ kh_status kh_hdeg(kh_graph *g, int32_t h, const uint8_t *alive, uint32_t flags, 
  * Q in {1,2,4,8,16} bit-plane words per vertex (the widest that fits is
  * used), must fit the array; at Q = 1 that is n up to about 5e5 at average
  * degree 10.
+ * The graph (its device CSR), alive and the outputs must stay valid until the
+ * enqueued work has completed (synchronise the stream before kh_graph_free).
  * Errors, decided on the host before anything is enqueued: KH_EINVAL (NULL
  * graph, NULL deg_out with n > 0, h < 1), KH_ENOMEM (the graph does not fit
  * the array); KH_EDEVICE when a launch fails. */
@@ -277,17 +299,19 @@ kh_status kh_dense(kh_graph *g, const kh_params *params, const int32_t *core_in,
 
 /* ---- measurement hooks ------------------------------------------------------ */
 
-/* Start (on != 0; resets the totals) or stop recording two kernels: the
- * h-degree pull kernel (kernel 0) and the sample-list union (kernel 1).  Every
- * launch is bracketed by HIP events on the stream it runs on (the round loops
- * then launch directly instead of replaying captured graphs), and the kernels
- * count the bytes they must move: for the pull kernel work items, adjacency
- * ids and visited/frontier words read and written, plus (separately) the
- * neighbour frontier words it gathers; for the union the adjacency metadata,
- * the list entries read and the list written. */
+/* Start (on != 0; resets the totals) or stop recording three kernels: the
+ * h-degree pull kernel (kernel 0), the sample-list union (kernel 1) and one hop
+ * of the exact peel's R-mask BFS (kernel 2, push or pull form).  Every launch is
+ * bracketed by HIP events on the stream it runs on (the round loops then launch
+ * directly instead of replaying captured graphs), and the kernels count the
+ * bytes they must move: for the pull kernel work items, adjacency ids and
+ * visited/frontier words read and written, plus (separately) the neighbour
+ * frontier words it gathers; for the union the adjacency metadata, the list
+ * entries read and the list written; for the mask BFS the frontier chunks or
+ * vertices, adjacency ids, alive flags and mask words read and written. */
 kh_status kh_profile_enable(kh_context *ctx, int32_t on);
 
-/* Totals for `kernel` (0 or 1) since kh_profile_enable(ctx, 1): launches,
+/* Totals for `kernel` (0, 1 or 2) since kh_profile_enable(ctx, 1): launches,
  * summed kernel time (ms), algorithmic bytes, and gathered bytes (kernel 0
  * only).  Any output pointer may be NULL.  Synchronises the recorded events. */
 kh_status kh_profile_read(kh_context *ctx, int32_t kernel, int64_t *launches, double *total_ms,

@@ -214,6 +214,8 @@ __device__ void round_reset_fields(RoundState* st) {
     for (int b = 0; b < 48; ++b) st->hist[b] = 0;
     st->fcount[0] = 0;
     st->fcount[1] = 0;
+    st->hop_arcs = 0;
+    st->next_arcs = 0;
     st->epoch += 1;
     st->fepoch += 1;  // frontier marks of the mask BFS's first hop
 }
@@ -228,11 +230,11 @@ void launch_round_reset(RoundState* st, hipStream_t s, int gate) {
 // min of key, sum of val and count over alive vertices (one atomic triple per block).
 __global__ __launch_bounds__(512) void k_reduce(const int64_t* __restrict__ key, const int64_t* __restrict__ val,
                                                 const uint8_t* __restrict__ alive, int32_t n, RoundState* st,
-                                                int gate) {
+                                                int gate, const uint8_t* __restrict__ exact) {
     if (gate && st->stall) return;
-    __shared__ long long smin[8], ssum[8];
+    __shared__ long long smin[8], ssum[8], sinx[8];
     __shared__ int scnt[8];
-    long long mn = LLONG_MAX, sm = 0;
+    long long mn = LLONG_MAX, sm = 0, mi = LLONG_MAX;
     int cnt = 0;
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         if (alive[v]) {
@@ -240,21 +242,25 @@ __global__ __launch_bounds__(512) void k_reduce(const int64_t* __restrict__ key,
             mn = k < mn ? k : mn;
             sm += val ? val[v] : 0;
             ++cnt;
+            if (exact && !exact[v]) mi = k < mi ? k : mi;
         }
     }
     mn = wave_min_ll(mn);
     sm = wave_sum_ll(sm);
+    mi = wave_min_ll(mi);
     cnt = wave_sum_i(cnt);
     const int w = threadIdx.x >> 6;
     if (lane_id() == 0) {
         smin[w] = mn;
         ssum[w] = sm;
+        sinx[w] = mi;
         scnt[w] = cnt;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
             mn = smin[i] < mn ? smin[i] : mn;
+            mi = sinx[i] < mi ? sinx[i] : mi;
             sm += ssum[i];
             cnt += scnt[i];
         }
@@ -262,13 +268,15 @@ __global__ __launch_bounds__(512) void k_reduce(const int64_t* __restrict__ key,
             atomicMin(&st->min_key, mn);
             if (sm) atomicAdd((unsigned long long*)&st->sum_val, (unsigned long long)sm);
             atomicAdd(&st->alive_count, cnt);
+            if (mi != LLONG_MAX) atomicMin(&st->min_inexact, mi);
         }
     }
 }
 void launch_reduce(const int64_t* key, const int64_t* val, const uint8_t* alive, int32_t n, RoundState* st,
-                   hipStream_t s, int gate) {
+                   hipStream_t s, int gate, const uint8_t* exact) {
     if (n > 0)
-        hipLaunchKernelGGL(k_reduce, dim3(grid_for(n, 512, 256)), dim3(512), 0, s, key, val, alive, n, st, gate);
+        hipLaunchKernelGGL(k_reduce, dim3(grid_for(n, 512, 256)), dim3(512), 0, s, key, val, alive, n, st, gate,
+                           exact);
 }
 
 // c = max(c, min key).  When c rises to K, the alive set is exactly
@@ -281,7 +289,7 @@ void launch_reduce(const int64_t* key, const int64_t* val, const uint8_t* alive,
 // numbers as testing after every single deletion: vertices leave in
 // non-decreasing core order and the test is weakest at the end of a level.
 __global__ void k_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_size, int64_t* cand_sum, int early_stop) {
-    if (st->alive_count == 0) return;
+    if (st->alive_count == 0 || st->stall) return;
     long long c = st->c;
     if (early_stop && st->rounds > 0 && c + 1 >= (long long)st->alive_count) {
         st->stop = 1;
@@ -309,9 +317,11 @@ void launch_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_size, int
 // R = {alive v : key[v] <= c} (all alive when the early stop fired): core = c.
 __global__ void k_select(const int64_t* __restrict__ key, uint8_t* __restrict__ alive, int32_t n, RoundState* st,
                          int64_t* __restrict__ core, int32_t* __restrict__ rlist, int32_t* __restrict__ mark,
-                         int32_t epoch, int kill) {
+                         int32_t epoch, int kill, int32_t* __restrict__ rnd) {
+    if (st->stall) return;  // a lazy activation takes this round's place
     const long long c = st->c;
     const int stop = st->stop;
+    const int32_t round_id = st->epoch;
     const int32_t stride = gridDim.x * blockDim.x;
     for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
         const int32_t v = base + threadIdx.x;
@@ -323,14 +333,15 @@ __global__ void k_select(const int64_t* __restrict__ key, uint8_t* __restrict__ 
             rlist[slot] = v;
             if (mark) mark[v] = epoch;
             if (kill) alive[v] = 0;
+            if (rnd) rnd[v] = round_id;
         }
     }
 }
 void launch_select(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core, int32_t* rlist,
-                   int32_t* mark, int32_t epoch, int kill, hipStream_t s) {
+                   int32_t* mark, int32_t epoch, int kill, hipStream_t s, int32_t* rnd) {
     if (n > 0)
         hipLaunchKernelGGL(k_select, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, key, alive, n, st, core, rlist,
-                           mark, epoch, kill);
+                           mark, epoch, kill, rnd);
 }
 
 __global__ void k_kill_list(const int32_t* __restrict__ list, const int* count, uint8_t* __restrict__ alive) {
@@ -346,17 +357,23 @@ void launch_kill_list(const int32_t* list, const int* count, uint8_t* alive, hip
 // that hubs are spread over many waves.
 __global__ void k_enqueue(const int32_t* __restrict__ list, const int* lo_p, const int* hi_p,
                           const int32_t* __restrict__ rp, int32_t* __restrict__ qv, int32_t* __restrict__ qb,
-                          int* qcount) {
+                          int* qcount, long long* arcs, const RoundState* pull_st, int64_t nnz) {
+    // a mask-BFS hop that pulls needs no chunk queue
+    if (pull_st && nnz > 0 && pull_st->hop_arcs * (long long)kRbfsPullRatio > nnz) return;
     const int lo = lo_p ? *lo_p : 0;
     const int hi = *hi_p;
     const int stride = gridDim.x * blockDim.x;
     for (int base = lo + blockIdx.x * blockDim.x; base < hi; base += stride) {
         const int i = base + threadIdx.x;
-        int v = 0, nch = 0;
+        int v = 0, nch = 0, d = 0;
         if (i < hi) {
             v = list[i];
-            const int d = rp[v + 1] - rp[v];
+            d = rp[v + 1] - rp[v];
             nch = (d + kExpandChunk - 1) / kExpandChunk;
+        }
+        if (arcs) {
+            const long long ws = wave_sum_ll((long long)d);
+            if (lane_id() == 0 && ws) atomicAdd((unsigned long long*)arcs, (unsigned long long)ws);
         }
         const int incl = wave_incl_scan(nch);
         const int total = __shfl(incl, 63);
@@ -371,18 +388,19 @@ __global__ void k_enqueue(const int32_t* __restrict__ list, const int* lo_p, con
     }
 }
 void launch_enqueue(const int32_t* list, const int* lo, const int* hi, const int32_t* rp, int32_t* qv, int32_t* qb,
-                    int* qcount, hipStream_t s) {
-    hipLaunchKernelGGL(k_enqueue, dim3(512), dim3(256), 0, s, list, lo, hi, rp, qv, qb, qcount);
+                    int* qcount, hipStream_t s, long long* arcs, const RoundState* pull_st, int64_t nnz) {
+    hipLaunchKernelGGL(k_enqueue, dim3(512), dim3(256), 0, s, list, lo, hi, rp, qv, qb, qcount, arcs, pull_st, nnz);
 }
 
 __global__ void k_enqueue_r(const int32_t* __restrict__ rlist, const int* rcount, const int32_t* __restrict__ rp,
                             int32_t* __restrict__ qv, int32_t* __restrict__ qb, int* qcount, int mode,
-                            uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain, uint8_t* __restrict__ alive) {
+                            uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain, uint8_t* __restrict__ alive,
+                            long long* arcs) {
     const int hi = *rcount;
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x; base < hi; base += stride) {
         const int i = base + threadIdx.x;
-        int v = 0, nch = 0;
+        int v = 0, nch = 0, d = 0;
         if (i < hi) {
             v = rlist[i];
             if (mode == 0) {
@@ -392,8 +410,12 @@ __global__ void k_enqueue_r(const int32_t* __restrict__ rlist, const int* rcount
             } else {
                 alive[v] = 0;
             }
-            const int d = rp[v + 1] - rp[v];
+            d = rp[v + 1] - rp[v];
             nch = (d + kExpandChunk - 1) / kExpandChunk;
+        }
+        if (arcs) {
+            const long long ws = wave_sum_ll((long long)d);
+            if (lane_id() == 0 && ws) atomicAdd((unsigned long long*)arcs, (unsigned long long)ws);
         }
         const int incl = wave_incl_scan(nch);
         const int total = __shfl(incl, 63);
@@ -408,9 +430,9 @@ __global__ void k_enqueue_r(const int32_t* __restrict__ rlist, const int* rcount
     }
 }
 void launch_enqueue_r(const int32_t* rlist, const int* rcount, const int32_t* rp, int32_t* qv, int32_t* qb, int* qcount,
-                      int mode, uint64_t* rmask, uint64_t* gain, uint8_t* alive, hipStream_t s) {
+                      int mode, uint64_t* rmask, uint64_t* gain, uint8_t* alive, hipStream_t s, long long* arcs) {
     hipLaunchKernelGGL(k_enqueue_r, dim3(256), dim3(256), 0, s, rlist, rcount, rp, qv, qb, qcount, mode, rmask, gain,
-                       alive);
+                       alive, arcs);
 }
 
 __global__ void k_expand(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
@@ -582,26 +604,41 @@ __global__ void k_anchor(const int32_t* __restrict__ list, const int* count, int
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int l = lane_id();
-    for (int i = wave; i < total; i += nwaves) {
-        const int32_t v = list ? list[i] : i;
-        if (!alive[v]) continue;
-        if (only_dead) {
-            const int32_t a = anchor[v];
-            if (a >= 0 && alive[a]) continue;
-        }
-        long long best = -1;
-        for (int32_t p = rp[v] + l; p < rp[v + 1]; p += 64) {
-            const int32_t w = col[p];
-            if (alive[w]) {
-                const long long key = ((long long)adeg[w] << 32) | (long long)(0x7FFFFFFF - w);
-                best = key > best ? key : best;
+    // a wave takes 64 entries (one per lane), and then walks the arcs of those
+    // whose anchor must be found again, all lanes on one vertex at a time
+    for (int base = wave * 64; base < total; base += nwaves * 64) {
+        const int i = base + l;
+        int32_t v = -1;
+        bool need = false;
+        if (i < total) {
+            v = list ? list[i] : i;
+            if (alive[v]) {
+                need = true;
+                if (only_dead) {
+                    const int32_t a = anchor[v];
+                    need = !(a >= 0 && alive[a]);
+                }
             }
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            const long long t = __shfl_xor(best, o);
-            best = t > best ? t : best;
+        unsigned long long todo = __ballot(need);
+        while (todo) {
+            const int src = __ffsll((long long)todo) - 1;
+            todo &= todo - 1ull;
+            const int32_t u = __shfl(v, src);
+            long long best = -1;
+            for (int32_t p = rp[u] + l; p < rp[u + 1]; p += 64) {
+                const int32_t w = col[p];
+                if (alive[w]) {
+                    const long long key = ((long long)adeg[w] << 32) | (long long)(0x7FFFFFFF - w);
+                    best = key > best ? key : best;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const long long t = __shfl_xor(best, o);
+                best = t > best ? t : best;
+            }
+            if (l == 0) anchor[u] = best < 0 ? -1 : (int32_t)(0x7FFFFFFF - (int32_t)(best & 0x7FFFFFFF));
         }
-        if (l == 0) anchor[v] = best < 0 ? -1 : (int32_t)(0x7FFFFFFF - (int32_t)(best & 0x7FFFFFFF));
     }
 }
 void launch_anchor(const int32_t* list, const int* count, int32_t n, const int32_t* rp, const int32_t* col,
@@ -870,7 +907,7 @@ void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact,
 
 __global__ void k_select_commit(const int64_t* __restrict__ key, uint8_t* __restrict__ alive, int32_t n,
                                 RoundState* st, int64_t* __restrict__ core, int32_t* __restrict__ rlist,
-                                int32_t* __restrict__ mark) {
+                                int32_t* __restrict__ mark, int32_t* __restrict__ rnd) {
     if (st->stall) return;
     // every block takes the same decision from the sweep's reductions; block 0 records it
     const long long c = cur_level(st);
@@ -894,14 +931,15 @@ __global__ void k_select_commit(const int64_t* __restrict__ key, uint8_t* __rest
             core[v] = c;
             rlist[slot] = v;
             mark[v] = epoch;
+            if (rnd) rnd[v] = epoch;
         }
     }
 }
 void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core,
-                          int32_t* rlist, int32_t* mark, hipStream_t s) {
+                          int32_t* rlist, int32_t* mark, hipStream_t s, int32_t* rnd) {
     if (n > 0)
         hipLaunchKernelGGL(k_select_commit, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, key, alive, n, st, core,
-                           rlist, mark);
+                           rlist, mark, rnd);
 }
 
 // ---- R-mask BFS of the lazy exact peel ---------------------------------------------------------
@@ -910,35 +948,65 @@ void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundSt
 // deg_h(v; X \ R) = deg_h(v; X) - |R ∩ N(v;h,X)|: an exact update.  The mask BFS
 // gives |R ∩ N(v;h,X)| as a popcount when |R| <= 64 (R's bits are set by
 // launch_enqueue_r).
+__device__ __forceinline__ bool rbfs_pulls(const RoundState* st, int64_t nnz) {
+    return nnz > 0 && st->hop_arcs * (long long)kRbfsPullRatio > nnz;
+}
+
+// Algorithmic bytes of a block of the mask BFS and the arcs of the vertices it
+// put on the next frontier: one atomic per block and counter.
+__device__ __forceinline__ void rbfs_count(unsigned long long bytes, long long next_arcs, RoundState* st) {
+    __shared__ unsigned long long red[2][16];
+    bytes = (unsigned long long)wave_sum_ll((long long)bytes);
+    next_arcs = wave_sum_ll(next_arcs);
+    if (lane_id() == 0) {
+        red[0][threadIdx.x >> 6] = bytes;
+        red[1][threadIdx.x >> 6] = (unsigned long long)next_arcs;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[threadIdx.x][w];
+        if (t) atomicAdd(threadIdx.x == 0 ? &st->rbfs_bytes : (unsigned long long*)&st->next_arcs, t);
+    }
+}
+
 __global__ void k_rbfs_expand(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
                               const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                               const uint8_t* __restrict__ alive, const uint64_t* __restrict__ gain_cur,
                               uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain_next, int32_t* __restrict__ mark,
                               int32_t epoch, int32_t* __restrict__ fmark, int32_t fepoch, int32_t* __restrict__ fnext,
-                              int* fnext_count, int32_t* __restrict__ alist, int* aff_fill, RoundState* st) {
+                              int* fnext_count, int32_t* __restrict__ alist, int* aff_fill, RoundState* st,
+                              int64_t nnz) {
+    if (rbfs_pulls(st, nnz)) return;  // the pull kernel takes this hop
     if (epoch < 0) epoch = st->epoch;
     if (fepoch < 0) fepoch = st->fepoch;
     const int nq = *qcount;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int l = lane_id();
+    unsigned long long bytes = 0;
+    long long next_arcs = 0;
     for (int q = wave; q < nq; q += nwaves) {
         const int32_t u = qv[q];
         const int32_t b = qb[q];
         const int32_t e = min(b + kExpandChunk, rp[u + 1]);
         const uint64_t g = gain_cur[u];
+        if (l == 0) bytes += 20;  // chunk (u, b), rp[u + 1], gain[u]
         for (int32_t p0 = b; p0 < e; p0 += 64) {
             const int32_t p = p0 + l;
             bool want_f = false, want_a = false;
             int32_t w = 0;
             if (p < e && g) {
                 w = col[p];
+                bytes += 5;  // id, alive
                 if (alive[w]) {
+                    bytes += 8;  // rmask
                     const uint64_t nb = g & ~rmask[w];
                     if (nb) {
                         const uint64_t old = atomicOr((unsigned long long*)&rmask[w], (unsigned long long)nb);
                         const uint64_t nw = nb & ~old;
                         if (nw) {
+                            bytes += 16;  // rmask, gain written
                             atomicOr((unsigned long long*)&gain_next[w], (unsigned long long)nw);
                             if (fmark[w] != fepoch) want_f = atomicExch(&fmark[w], fepoch) != fepoch;
                             if (mark[w] != epoch) want_a = atomicExch(&mark[w], epoch) != epoch;
@@ -947,23 +1015,108 @@ __global__ void k_rbfs_expand(const int32_t* __restrict__ qv, const int32_t* __r
                 }
             }
             const int sf = wave_append_slot(want_f, fnext_count);
-            if (want_f) fnext[sf] = w;
+            if (want_f) {
+                fnext[sf] = w;
+                next_arcs += rp[w + 1] - rp[w];
+            }
             const int sa = wave_append_slot(want_a, aff_fill);
             if (want_a) alist[sa] = w;
+            bytes += (want_f ? 12 : 0) + (want_a ? 4 : 0);
         }
     }
+    rbfs_count(bytes, next_arcs, st);
 }
 void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
                         const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
                         int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
-                        int32_t* alist, int* aff_fill, RoundState* st, hipStream_t s) {
+                        int32_t* alist, int* aff_fill, RoundState* st, hipStream_t s, int64_t nnz) {
     hipLaunchKernelGGL(k_rbfs_expand, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, gain_cur, rmask,
-                       gain_next, mark, epoch, fmark, fepoch, fnext, fnext_count, alist, aff_fill, st);
+                       gain_next, mark, epoch, fmark, fepoch, fnext, fnext_count, alist, aff_fill, st, nnz);
+}
+
+// Pull form of a hop: vertex w gets new = (OR over alive neighbours u of
+// gain_cur[u]) & ~rmask[w] -- the union of what the frontier would push to it
+// (gain_cur is zero off the frontier and on deleted vertices, which never carry
+// bits).  One thread owns w, so no atomics; the scan of w's arcs stops once w
+// holds every bit of R (full), which for the one- and two-vertex deletions of a
+// long peel is usually after the first frontier neighbour.
+__global__ __launch_bounds__(256) void k_rbfs_pull(int32_t n, const int32_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col,
+                                                   const uint8_t* __restrict__ alive,
+                                                   const uint64_t* __restrict__ gain_cur,
+                                                   uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain_next,
+                                                   int32_t* __restrict__ mark, int32_t* __restrict__ fnext,
+                                                   int* fnext_count, int32_t* __restrict__ alist, int* aff_fill,
+                                                   RoundState* st, int64_t nnz) {
+    if (!rbfs_pulls(st, nnz)) return;
+    const int32_t epoch = st->epoch;
+    const int rc = st->rcount;
+    const uint64_t full = rc >= 64 ? ~0ull : ((1ull << rc) - 1ull);
+    unsigned long long bytes = 0;
+    long long next_arcs = 0;
+    const int32_t stride = gridDim.x * blockDim.x;
+    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int32_t w = base + threadIdx.x;
+        bool front = false, first = false;
+        if (w < n) {
+            bytes += 1;
+            if (alive[w]) {
+                const uint64_t have = rmask[w];
+                bytes += 8;
+                if (have != full) {
+                    const int32_t b = rp[w], e = rp[w + 1];
+                    bytes += 8;
+                    uint64_t acc = 0ull;
+                    int32_t p = b;
+                    while (p < e) {
+                        acc |= gain_cur[col[p++]];
+                        if ((acc | have) == full) break;
+                    }
+                    bytes += 12ull * (unsigned long long)(p - b);  // ids and the neighbours' masks read
+                    const uint64_t nw = acc & ~have;
+                    if (nw) {
+                        rmask[w] = have | nw;
+                        gain_next[w] = nw;
+                        front = true;
+                        next_arcs += e - b;
+                        first = mark[w] != epoch;
+                        if (first) mark[w] = epoch;
+                        bytes += 20;
+                    }
+                }
+            }
+        }
+        const int sf = wave_append_slot(front, fnext_count);
+        if (front) fnext[sf] = w;
+        const int sa = wave_append_slot(first, aff_fill);
+        if (first) alist[sa] = w;
+        bytes += (front ? 4 : 0) + (first ? 4 : 0);
+    }
+    rbfs_count(bytes, next_arcs, st);
+}
+
+void launch_rbfs_hop(const int32_t* qv, const int32_t* qb, const int* qcount, int32_t n, const int32_t* rp,
+                     const int32_t* col, const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask,
+                     uint64_t* gain_next, int32_t* mark, int32_t* fmark, int32_t* fnext, int* fnext_count,
+                     int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz, hipStream_t s, PullTimer* timer) {
+    const bool timed = timer && timer->used < timer->cap;
+    if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
+    hipLaunchKernelGGL(k_rbfs_expand, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, gain_cur, rmask,
+                       gain_next, mark, -1, fmark, -1, fnext, fnext_count, alist, aff_fill, st, nnz);
+    if (n > 0)
+        hipLaunchKernelGGL(k_rbfs_pull, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, rp, col, alive, gain_cur,
+                           rmask, gain_next, mark, fnext, fnext_count, alist, aff_fill, st, nnz);
+    if (timed) {
+        (void)hipEventRecord(timer->ev[2 * timer->used + 1], s);
+        timer->used += 1;
+    }
 }
 
 __global__ void k_hop_end(RoundState* st, int* hopfill, int t, int h) {
     hopfill[t] = st->aff_fill;
     st->qcount = 0;
+    st->hop_arcs = st->next_arcs;  // the next hop's frontier
+    st->next_arcs = 0;
     if (t < h) {
         st->fepoch += 1;
         st->fcount[(t + 1) & 1] = 0;

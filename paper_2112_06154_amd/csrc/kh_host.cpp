@@ -20,12 +20,14 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <map>
 #include <mutex>
 #include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <stdexcept>
 #include <vector>
@@ -72,10 +74,17 @@ struct kh_context {
     std::vector<RoundState*> pool;
     // pull-kernel timing (kh_profile_enable / kh_profile_read)
     bool prof_on = false;
-    PullTimer timer[2];  // 0: h-degree pull, 1: sample-list union
-    long long prof_launches[2] = {0, 0};
-    double prof_ms[2] = {0.0, 0.0};
-    unsigned long long prof_bytes[2] = {0, 0}, prof_gather = 0;
+    PullTimer timer[3];  // 0: h-degree pull, 1: sample-list union, 2: R-mask BFS hop
+    long long prof_launches[3] = {0, 0, 0};
+    double prof_ms[3] = {0.0, 0.0, 0.0};
+    unsigned long long prof_bytes[3] = {0, 0, 0}, prof_gather = 0;
+    // idle device blocks kept for reuse, by size: hipFree waits for the whole
+    // device, which would serialise calls running on several streams (served
+    // requests), and most calls allocate the same sizes again
+    std::mutex cache_lock;
+    std::multimap<size_t, void*> cache;
+    uint64_t cached = 0;      // bytes held in `cache`
+    uint64_t cache_cap = 0;   // most bytes `cache` may hold
 };
 
 namespace {
@@ -124,6 +133,69 @@ struct StateLease {
     StateLease& operator=(const StateLease&) = delete;
 };
 
+// Device blocks come in size classes (powers of two up to 1 MiB, then whole
+// MiB) so that a block released by one call fits the next call's request.
+size_t block_bytes(size_t bytes) {
+    if (bytes <= ((size_t)1 << 20)) {
+        size_t b = 256;
+        while (b < bytes) b <<= 1;
+        return b;
+    }
+    return (bytes + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+}
+
+// Give every cached block back to the device (waits for the device).
+void cache_flush(kh_context* ctx) {
+    std::lock_guard<std::mutex> lk(ctx->cache_lock);
+    for (auto& kv : ctx->cache) (void)hipFree(kv.second);
+    ctx->cache.clear();
+    ctx->cached = 0;
+}
+
+// A device block of exactly `bytes` (a size class): a cached one, else hipMalloc.
+// Blocks only enter the cache when the call that used them has synchronised its
+// streams (every entry point does before its buffers are released), so a block
+// taken from the cache is idle.
+void* device_take(kh_context* ctx, size_t bytes) {
+    {
+        std::lock_guard<std::mutex> lk(ctx->cache_lock);
+        auto it = ctx->cache.find(bytes);
+        if (it != ctx->cache.end()) {
+            void* p = it->second;
+            ctx->cache.erase(it);
+            ctx->cached -= bytes;
+            return p;
+        }
+    }
+    if (ctx->budget && ctx->used.load() + ctx->cached + bytes > ctx->budget) cache_flush(ctx);
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        cache_flush(ctx);
+        e = hipMalloc(&q, bytes);
+    }
+    hip_ok(e);
+    return q;
+}
+
+void device_give(kh_context* ctx, void* p, size_t bytes) {
+    if (std::uncaught_exceptions() > 0) {
+        // a call that failed may still have kernels in flight: hipFree waits for them
+        (void)hipFree(p);
+        return;
+    }
+    {
+        std::lock_guard<std::mutex> lk(ctx->cache_lock);
+        if (ctx->cached + bytes <= ctx->cache_cap) {
+            ctx->cache.emplace(bytes, p);
+            ctx->cached += bytes;
+            return;
+        }
+    }
+    (void)hipFree(p);
+}
+
 template <typename T>
 struct Buf {
     kh_context* ctx = nullptr;
@@ -151,23 +223,25 @@ struct Buf {
     void alloc(kh_context* c, size_t n) {
         release();
         ctx = c;
-        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        const size_t bytes = block_bytes(std::max<size_t>(n, 1) * sizeof(T));
         const uint64_t before = ctx->used.fetch_add(bytes);
         if (ctx->budget && before + bytes > ctx->budget) {
             ctx->used.fetch_sub(bytes);
             fail(KH_ENOMEM);
         }
-        void* q = nullptr;
-        const hipError_t e = hipMalloc(&q, bytes);
-        if (e != hipSuccess) ctx->used.fetch_sub(bytes);
-        hip_ok(e);
-        p = static_cast<T*>(q);
+        try {
+            p = static_cast<T*>(device_take(ctx, bytes));
+        } catch (...) {
+            ctx->used.fetch_sub(bytes);
+            throw;
+        }
         count = n;
     }
     void release() {
         if (p) {
-            (void)hipFree(p);
-            ctx->used -= std::max<size_t>(count, 1) * sizeof(T);
+            const size_t bytes = block_bytes(std::max<size_t>(count, 1) * sizeof(T));
+            device_give(ctx, p, bytes);
+            ctx->used -= bytes;
             p = nullptr;
             count = 0;
         }
@@ -275,6 +349,8 @@ extern "C" kh_status kh_context_create(int32_t device, uint64_t hbm_budget_bytes
     ctx->budget = hbm_budget_bytes;
     ctx->lds_per_block = prop.sharedMemPerBlock;
     ctx->num_cu = prop.multiProcessorCount;
+    // idle blocks kept for reuse: at most a quarter of the budget (or of the device)
+    ctx->cache_cap = (hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)prop.totalGlobalMem) / 4;
     void* hs = nullptr;
     if (hipHostMalloc(&hs, sizeof(RoundState), hipHostMallocDefault) != hipSuccess) {
         delete ctx;
@@ -307,6 +383,7 @@ kh_context* graph_context(const kh_graph* g);
 extern "C" void kh_context_destroy(kh_context* ctx) {
     if (!ctx) return;
     kh::serve_shutdown(ctx);
+    cache_flush(ctx);
     if (ctx->host_state) (void)hipHostFree(ctx->host_state);
     for (RoundState* p : ctx->pool) (void)hipHostFree(p);
     for (auto& T : ctx->timer) {
@@ -322,7 +399,7 @@ namespace {
 
 // Fold the recorded launches into the context totals.
 void prof_collect(kh_context* ctx) {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         PullTimer& T = ctx->timer[k];
         for (int i = 0; i < T.used; ++i) {
             float ms = 0.f;
@@ -341,6 +418,7 @@ void prof_add_counters(kh_context* ctx, const RoundState& hs) {
     ctx->prof_bytes[0] += hs.pull_bytes;
     ctx->prof_gather += hs.pull_gather;
     ctx->prof_bytes[1] += hs.union_bytes;
+    ctx->prof_bytes[2] += hs.rbfs_bytes;
 }
 
 }  // namespace
@@ -360,7 +438,7 @@ extern "C" kh_status kh_profile_enable(kh_context* ctx, int32_t on) {
         if (ctx->prof_on) prof_collect(ctx);
         ctx->prof_on = on != 0;
         if (on) {
-            for (int k = 0; k < 2; ++k) {
+            for (int k = 0; k < 3; ++k) {
                 ctx->timer[k].used = 0;
                 ctx->prof_launches[k] = 0;
                 ctx->prof_ms[k] = 0.0;
@@ -376,7 +454,7 @@ extern "C" kh_status kh_profile_enable(kh_context* ctx, int32_t on) {
 
 extern "C" kh_status kh_profile_read(kh_context* ctx, int32_t kernel, int64_t* launches, double* total_ms,
                                      int64_t* alg_bytes, int64_t* gather_bytes) {
-    if (!ctx || kernel < 0 || kernel > 1) return KH_EINVAL;
+    if (!ctx || kernel < 0 || kernel > 2) return KH_EINVAL;
     try {
         if (ctx->prof_on) prof_collect(ctx);
     } catch (const KhError& e) {
@@ -509,6 +587,30 @@ bool trace_on() {
     }();
     return on;
 }
+
+// Opt-in heartbeat on stderr (KH_HEARTBEAT=<seconds>): a line at most every
+// that many seconds from the long round loops, so that a caller watching the
+// output can tell a long peel from a stuck one.
+double heartbeat_every() {
+    static const double s = [] {
+        const char* e = std::getenv("KH_HEARTBEAT");
+        return e && e[0] ? std::atof(e) : 0.0;
+    }();
+    return s;
+}
+
+struct Heartbeat {
+    Clock::time_point t0 = Clock::now(), last = Clock::now();
+    void tick(const char* what, const RoundState& hs) {
+        const double every = heartbeat_every();
+        if (every <= 0.0) return;
+        const auto now = Clock::now();
+        if (std::chrono::duration<double>(now - last).count() < every) return;
+        last = now;
+        std::fprintf(stderr, "[kh] %s: round %d, c %lld, %d alive, %.1fs\n", what, hs.rounds, hs.c, hs.alive_count,
+                     std::chrono::duration<double>(now - t0).count());
+    }
+};
 
 void check_params(const kh_graph* g, const kh_params* P) {
     if (!g || !P) fail(KH_EINVAL);
@@ -848,6 +950,7 @@ struct ExactRun {
     Candidates cands;
     RoundState fin{};
     long long recomputed = 0;  // exact h-degree evaluations
+    int32_t* rnd_out = nullptr;  // nullable: deletion round (epoch) of every vertex
 
     void alloc(int32_t n) {
         kh_context* ctx = g->ctx;
@@ -906,16 +1009,20 @@ struct ExactRun {
     // committed.
     void delete_round_masked() {
         // R's mask bits and the chunks of hop 1 (the round reset zeroed qcount)
-        launch_enqueue_r(rlist.p, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, 0, rmask.p, gainA.p, nullptr, s);
+        launch_enqueue_r(rlist.p, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, 0, rmask.p, gainA.p, nullptr, s,
+                         &st.p->hop_arcs);
         int32_t* fl[2] = {flA.p, flB.p};
         uint64_t* gain[2] = {gainA.p, gainB.p};
+        PullTimer* rt = prof_active(g->ctx) ? &g->ctx->timer[2] : nullptr;
         for (int t = 1; t <= h; ++t) {
             const int32_t* src = t == 1 ? rlist.p : fl[(t - 1) & 1];
             const int* srcn = t == 1 ? &st.p->rcount : &st.p->fcount[(t - 1) & 1];
-            if (t > 1) launch_enqueue(src, nullptr, srcn, g->rp, qv.p, qb.p, &st.p->qcount, s);
-            launch_rbfs_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, gain[(t - 1) & 1], rmask.p,
-                               gain[t & 1], mark.p, -1, fmark.p, -1, fl[t & 1], &st.p->fcount[t & 1], alist.p,
-                               &st.p->aff_fill, st.p, s);
+            if (t > 1) launch_enqueue(src, nullptr, srcn, g->rp, qv.p, qb.p, &st.p->qcount, s, nullptr, st.p, g->nnz);
+            // push from the frontier's chunks, or pull into every alive vertex
+            // when the frontier holds more than 1/kRbfsPullRatio of the arcs
+            launch_rbfs_hop(qv.p, qb.p, &st.p->qcount, g->n, g->rp, g->col, alive.p, gain[(t - 1) & 1], rmask.p,
+                            gain[t & 1], mark.p, fmark.p, fl[t & 1], &st.p->fcount[t & 1], alist.p, &st.p->aff_fill,
+                            st.p, g->nnz, s, rt);
             launch_clear_u64_list(src, srcn, gain[(t - 1) & 1], s);
             launch_hop_end(st.p, hopfill.p, t, h, s);
         }
@@ -992,7 +1099,7 @@ struct ExactRun {
             // by the recompute sequence, or before the first replay)
             for (int r = 0; r < iters_per; ++r) {
                 launch_reduce_hist(deg.p, alive.p, exact.p, n, st.p, s);
-                launch_select_commit(deg.p, alive.p, n, st.p, core.p, rlist.p, mark.p, s);
+                launch_select_commit(deg.p, alive.p, n, st.p, core.p, rlist.p, mark.p, s, rnd_out);
                 delete_round_masked();
                 launch_anchor(alist.p, &st.p->aff_fill, n, g->rp, g->col, alive.p, adeg.p, anchor.p, 1, s);
                 launch_decay_masked(alist.p, st.p, hopfill.p, h, alive.p, adeg.p, anchor.p, rmask.p, deg.p, exact.p,
@@ -1030,6 +1137,24 @@ struct ExactRun {
         PL.timer = prof_active(ctx) ? &ctx->timer[0] : nullptr;
         const hipStream_t q = rp.prepare(caller, use_graph, record_long);
         const int i_short = rp.add(record_short);
+        // Commit sequences of several lengths: once a sequence stalls, its
+        // remaining iterations only launch kernels that return at once, so the
+        // host replays the length closest to the rounds it expects before the
+        // next stall (a running average of the rounds between stalls).  Small
+        // graphs keep the two lengths (capture costs more than it saves there).
+        std::vector<std::pair<int, int>> seqs = {{short_iters, i_short}, {long_iters, 0}};
+        if (n >= 100000) {
+            // (launched directly when not captured: any length then costs nothing up front)
+            for (int L : {4, 8, 16}) seqs.push_back({L, rp.add([&, L](hipStream_t qs) { commit_body(qs, L); })});
+            std::sort(seqs.begin(), seqs.end());
+        }
+        auto pick_len = [&](double want) -> std::pair<int, int> {
+            for (const auto& sq : seqs)
+                if ((double)sq.first >= want) return sq;
+            return seqs.back();
+        };
+        double ema_run = long_iters;  // rounds between stalls
+        long long rounds_prev = 0, since_stall = 0;
         // One graph: the host reads how many sources were picked and replays the
         // BFS captured for the narrowest bit planes that hold them (a batch of
         // 40 sources does not need 16 words per vertex).  A packed union keeps
@@ -1045,6 +1170,7 @@ struct ExactRun {
             i_rec = rp.add(record_recompute);
         }
         bool stalled = false;
+        Heartbeat hb;
         for (;;) {
             if (stalled) {
                 if (adaptive) {
@@ -1061,14 +1187,21 @@ struct ExactRun {
                 rp.run(record_short, i_short);
                 iters += short_iters + 1;
             } else {
-                rp.run(record_long, 0);
-                iters += long_iters;
+                const auto sq = pick_len(ema_run - (double)since_stall);
+                rp.run([&](hipStream_t qs) { commit_body(qs, sq.first); }, sq.second);
+                iters += sq.first;
             }
             if (prof_active(ctx)) prof_collect(ctx);
             read_state(ctx, st.p, q);
             const RoundState hs = *hstate(ctx);
             if (hs.mode == 2) break;
             stalled = hs.stall != 0;
+            since_stall += hs.rounds - rounds_prev;
+            rounds_prev = hs.rounds;
+            if (stalled) {
+                ema_run = 0.75 * ema_run + 0.25 * (double)since_stall;
+                since_stall = 0;
+            }
             if (iters > 8ll * n + 4096) fail(KH_EDEVICE);
             if (hs.fepoch > (1 << 30)) {
                 // frontier marks are compared for equality only: restart their epochs
@@ -1076,6 +1209,7 @@ struct ExactRun {
                 launch_set_int(&st.p->fepoch, 0, q);
             }
             trace_round(hs, "lazy", t0);
+            hb.tick("ExactCore", hs);
         }
         hip_ok(hipStreamSynchronize(q));
         fin = *hstate(ctx);
@@ -1168,12 +1302,16 @@ struct SampledRun {
     uint64_t seed;
     uint32_t stream_id;
     bool early_stop = false;
+    // lazy initialisation of level h (Sec. 5 heuristic): B[v,h] is built only once
+    // the lower bound from the neighbours' level h-1 lists no longer keeps v above c
+    bool lazy = false;
+    int32_t* rnd_out = nullptr;  // nullable: deletion round (epoch) of every vertex
     hipStream_t s;
     // packed batches: per-vertex M (nullable; M is then the largest) and the
     // vertex's id inside its own graph, from which its rank is drawn
     const int32_t* Mv = nullptr;
     const int32_t* lid = nullptr;
-    Buf<uint8_t> alive, rank;
+    Buf<uint8_t> alive, rank, active;
     Buf<int32_t> mark, rlist, wl, rc, hubs, lostmax, chA, chB, qv, qb, cursor, order;
     Buf<int64_t> d, core, ck, cs, cr, partials;
     Buf<RoundState> st;
@@ -1256,15 +1394,24 @@ struct SampledRun {
                       s);
         kh_context* ctx = g->ctx;
         PullTimer* utimer = prof_active(ctx) ? &ctx->timer[1] : nullptr;
-        for (int i = 2; i <= h; ++i) {
+        for (int i = 2; i <= (lazy ? h - 1 : h); ++i) {
             if (utimer && utimer->used + 2 >= utimer->cap) prof_collect(ctx);
             launch_union(nullptr, nullptr, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.hash_log2, L.view(i - 1),
                          L.view(i), cursor.p, order.p, nullptr, nullptr, st.p, s, utimer);
         }
-        launch_estimate(nullptr, nullptr, n, alive.p, rank.p, L.size[h].p, L.kk[h].p, M, Mv, d.p, st.p, s);
+        if (lazy) {
+            // every vertex starts inactive at level h, its estimate replaced by the bound
+            active.alloc(g->ctx, n);
+            hip_ok(hipMemsetAsync(active.p, 0, (size_t)n, s));
+            launch_lazy_lb(nullptr, nullptr, n, g->rp, g->col, alive.p, active.p, rank.p, M, Mv, L.view(h - 1), d.p,
+                           lostmax.p, s);
+        } else {
+            launch_estimate(nullptr, nullptr, n, alive.p, rank.p, L.size[h].p, L.kk[h].p, M, Mv, d.p, st.p, s);
+        }
     }
 
     void setup(const uint8_t* alive_in) {
+        lazy = lazy && h >= 2;
         alloc_common();
         init_state(st.p, s);
         launch_alive_from(alive_in, alive.p, g->n, s);
@@ -1290,12 +1437,24 @@ struct SampledRun {
         PullTimer* utimer = prof_active(ctx) ? &ctx->timer[1] : nullptr;
         const hipStream_t caller = s;
         Replay rp;
+        const bool lz = lazy && key_ext == nullptr;
         auto record = [&](hipStream_t q) {
             for (int r = 0; r < batch; ++r) {
                 launch_round_reset(st.p, q);
-                launch_reduce(key, d.p, alive.p, n, st.p, q);
+                launch_reduce(key, d.p, alive.p, n, st.p, q, 0, lz ? active.p : nullptr);
+                if (lz) {
+                    // when an inactive bound is at or below c' = max(c, min d), this
+                    // iteration activates every such vertex instead of deleting:
+                    // its level-h list is built from scratch, then its estimate
+                    launch_lazy_decide(st.p, q);
+                    launch_lazy_pick(alive.p, active.p, d.p, n, st.p, rc.p, q);
+                    launch_union(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.hash_log2,
+                                 L.view(h - 1), L.view(h), cursor.p, order.p, nullptr, nullptr, st.p, q, utimer);
+                    launch_estimate(rc.p, &st.p->rc_count, n, alive.p, rank.p, L.size[h].p, L.kk[h].p, M, Mv, d.p,
+                                    st.p, q);
+                }
                 launch_round_begin(st.p, ck.p, cs.p, cr.p, early_stop ? 1 : 0, q);
-                launch_select(key, alive.p, n, st.p, core.p, rlist.p, nullptr, 0, 1, q);
+                launch_select(key, alive.p, n, st.p, core.p, rlist.p, nullptr, 0, 1, q, rnd_out);
                 for (int i = 1; i <= h; ++i) {
                     launch_level_reset(st.p, i, q);
                     launch_enqueue(rlist.p, nullptr, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, q);
@@ -1304,9 +1463,14 @@ struct SampledRun {
                                        qb.p, &st.p->qcount, q);
                     launch_expand_lists(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, rank.p, mark.p, -1, i,
                                         L.view(i - 1), L.view(i), lostmax.p, wl.p, &st.p->wl_count, st.p, q);
+                    // inactive vertices of a lazy level h get a new bound from the level h-1 lists
+                    const bool lzh = lz && i == h;
+                    if (lzh)
+                        launch_lazy_lb(wl.p, &st.p->wl_count, n, g->rp, g->col, alive.p, active.p, rank.p, M, Mv,
+                                       L.view(h - 1), d.p, lostmax.p, q);
                     // levels >= 2: hubs are merged by the wide-block variant of the union kernel
                     launch_classify(wl.p, &st.p->wl_count, L.view(i), lostmax.p, rc.p, &st.p->rc_count, q, g->rp,
-                                    i > 1 ? hubs.p : nullptr, &st.p->hub_count);
+                                    i > 1 ? hubs.p : nullptr, &st.p->hub_count, lzh ? active.p : nullptr);
                     if (i == 1)
                         launch_union1(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.view(1),
                                       changed[1], &st.p->changed_count[1], st.p, q);
@@ -1320,13 +1484,18 @@ struct SampledRun {
             }
         };
         const hipStream_t q = rp.prepare(caller, !graphs_off() && !prof_active(ctx), record);
+        long long iters = 0;
+        Heartbeat hb;
         for (;;) {
             rp.run(record);
+            iters += batch;
             if (prof_active(ctx)) prof_collect(ctx);
             read_state(ctx, st.p, q);
             if (hstate(ctx)->alive_count == 0) break;
-            // every round deletes at least the minimum vertex
-            if (hstate(ctx)->rounds > n + 1) fail(KH_EDEVICE);
+            // every round deletes at least the minimum vertex, every lazy
+            // activation activates at least one vertex
+            if (hstate(ctx)->rounds > n + 1 || iters > 2ll * n + 64) fail(KH_EDEVICE);
+            hb.tick(key_ext ? "replay" : "Core", *hstate(ctx));
             if (trace_on() && ((hstate(ctx)->rounds & 255) < batch))
                 std::fprintf(stderr, "[kh sampled] round %d c %lld alive %d removed %d worklist %d merged %d t %.3fs\n",
                              hstate(ctx)->rounds, hstate(ctx)->c, hstate(ctx)->alive_count,
@@ -1444,6 +1613,101 @@ void dense_exact(kh_graph* g, const kh_params* P, const int64_t* core_dev, int64
     res->arcs_scanned += (int64_t)E.fin.arcs;
 }
 
+// Start set of the pruning variant (end of Sec. 6): {v : core(v) (1 + eps) >=
+// (1 - eps) max core}, eps = 0 for an exact map (only the innermost core).
+void prune_mask(kh_graph* g, const int64_t* core_dev, int64_t maxcore, double eps, Buf<uint8_t>& start,
+                hipStream_t s) {
+    std::vector<int64_t> hc((size_t)g->n);
+    hip_ok(hipMemcpyAsync(hc.data(), core_dev, 8 * (size_t)g->n, hipMemcpyDeviceToHost, s));
+    hip_ok(hipStreamSynchronize(s));
+    const double e = std::min(std::max(eps, 0.0), 0.999999);
+    std::vector<uint8_t> a((size_t)g->n);
+    for (int32_t v = 0; v < g->n; ++v) a[v] = (double)hc[v] * (1.0 + e) >= (1.0 - e) * (double)maxcore;
+    start.alloc(g->ctx, g->n);
+    hip_ok(hipMemcpyAsync(start.p, a.data(), (size_t)g->n, hipMemcpyHostToDevice, s));
+    hip_ok(hipStreamSynchronize(s));
+}
+
+// Alg. 7 over every suffix of the peel's deletion order (flag KH_DENSE_FULL).
+// The order: rounds in sequence, inside a round by the key at deletion (key_dev:
+// the estimate, or deg_h), then by k[v,h] (lev_dev, nullable for ExactCore),
+// then by id.  The replay deletes one vertex per round in that order (key =
+// position), recording sum f over the remaining suffix before each deletion,
+// with fresh ranks and M from C = log(n^2/delta) on the sampled path.
+void dense_full(kh_graph* g, const kh_params* P, const int64_t* core_dev, const int64_t* key_dev,
+                const uint8_t* lev_dev, const int32_t* rnd_dev, int64_t maxcore, bool sampled, kh_result* res,
+                hipStream_t s) {
+    kh_context* ctx = g->ctx;
+    const int32_t n = g->n;
+    Buf<int32_t> order;
+    Buf<int64_t> pos;
+    order.alloc(ctx, n);
+    pos.alloc(ctx, n);
+    {
+        Buf<uint32_t> lk, lk2;
+        Buf<int32_t> ids, ids2;
+        Buf<uint64_t> mk, mk2;
+        Buf<unsigned char> temp;
+        Buf<int> bad;
+        lk.alloc(ctx, n);
+        lk2.alloc(ctx, n);
+        ids.alloc(ctx, n);
+        ids2.alloc(ctx, n);
+        mk.alloc(ctx, n);
+        mk2.alloc(ctx, n);
+        OrderScratch w{lk.p, lk2.p, ids.p, ids2.p, mk.p, mk2.p, nullptr, order_temp_bytes(n)};
+        temp.alloc(ctx, w.temp_bytes);
+        w.temp = temp.p;
+        bad.alloc(ctx, 1);
+        launch_set_int(bad.p, 0, s);
+        hip_ok(deletion_order(n, rnd_dev, key_dev, lev_dev, w, order.p, pos.p, bad.p, s));
+        int hbad = 0;
+        hip_ok(hipMemcpyAsync(&hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        hip_ok(hipStreamSynchronize(s));
+        if (hbad) fail(KH_EOVERFLOW);
+    }
+    const bool prune = (P->flags & KH_DENSE_PRUNE) != 0;
+    Buf<uint8_t> start;
+    if (prune) prune_mask(g, core_dev, maxcore, sampled ? P->epsilon : 0.0, start, s);
+    const uint8_t* alive_in = prune ? start.p : nullptr;
+    Candidates C;
+    if (sampled) {
+        SampledRun R;
+        R.g = g;
+        R.h = effective_h(g, P->h);
+        R.M = resolve_M(g, P, true);
+        R.seed = P->seed;
+        R.stream_id = 1;
+        R.s = s;
+        R.setup(alive_in);
+        R.peel(pos.p);
+        C = R.cands;
+        res->M_dense_used = R.M;
+        res->list_elements += (int64_t)R.fin.elems;
+    } else {
+        ExactRun E;
+        E.g = g;
+        E.h = effective_h(g, P->h);
+        E.s = s;
+        E.run_replay(alive_in, pos.p);
+        C = E.cands;
+        res->edges_traversed += (int64_t)E.fin.te;
+        res->arcs_scanned += (int64_t)E.fin.arcs;
+    }
+    // candidates are positions; ties go to the later suffix (the smaller set)
+    pick_dense(C, false, 0.0, 0, res);
+    if (res->dense_k >= 0) {
+        // report the smallest core number in the chosen suffix: that of its first vertex
+        int32_t v = 0;
+        int64_t c = 0;
+        hip_ok(hipMemcpyAsync(&v, order.p + res->dense_k, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        hip_ok(hipStreamSynchronize(s));
+        hip_ok(hipMemcpyAsync(&c, core_dev + v, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        hip_ok(hipStreamSynchronize(s));
+        res->dense_k = c;
+    }
+}
+
 void clear_result(kh_result* r) {
     std::memset(r, 0, sizeof(*r));
     r->dense_k = -1;
@@ -1472,17 +1736,26 @@ extern "C" kh_status kh_core(kh_graph* g, const kh_params* P, int32_t* core_out,
             return KH_OK;
         }
         const int h = effective_h(g, P->h);
+        const bool full_dense = want_dense && (P->flags & KH_DENSE_FULL);
+        Buf<int32_t> rnd;
+        if (full_dense) {
+            if (P->epsilon > 0.0 && (P->flags & KH_EARLY_STOP)) fail(KH_ENOTIMPL);
+            rnd.alloc(g->ctx, g->n);
+            launch_fill_i32(rnd.p, -1, g->n, s);
+        }
         if (P->epsilon <= 0.0) {
             ExactRun E;
             E.g = g;
             E.h = h;
             E.s = s;
+            E.rnd_out = rnd.p;
             E.run_lazy();
             finish_core(g->ctx, E.core.p, g->n, core_out, out_dev, s, &R->max_core);
             R->rounds = E.fin.rounds;
             R->edges_traversed = (int64_t)E.fin.te;
             R->arcs_scanned = (int64_t)E.fin.arcs;
-            if (want_dense) dense_exact(g, P, E.core.p, R->max_core, R, s);
+            if (full_dense) dense_full(g, P, E.core.p, E.deg.p, nullptr, rnd.p, R->max_core, false, R, s);
+            else if (want_dense) dense_exact(g, P, E.core.p, R->max_core, R, s);
         } else {
             if (g->n > kMaxSampledN) fail(KH_ENOTIMPL);
             SampledRun S;
@@ -1492,6 +1765,8 @@ extern "C" kh_status kh_core(kh_graph* g, const kh_params* P, int32_t* core_out,
             S.seed = P->seed;
             S.stream_id = 0;
             S.early_stop = (P->flags & KH_EARLY_STOP) != 0;
+            S.lazy = (P->flags & KH_LAZY_INIT) != 0;
+            S.rnd_out = rnd.p;
             S.s = s;
             S.setup(nullptr);
             S.peel(nullptr);
@@ -1503,7 +1778,10 @@ extern "C" kh_status kh_core(kh_graph* g, const kh_params* P, int32_t* core_out,
             if (want_dense) {
                 // free the core pass's lists before the dense pass allocates its own
                 for (auto& k : S.L.keys) k.release();
-                dense_sampled(g, P, S.core.p, R->max_core, R, s);
+                if (full_dense)
+                    dense_full(g, P, S.core.p, S.d.p, S.L.kk[(size_t)h].p, rnd.p, R->max_core, true, R, s);
+                else
+                    dense_sampled(g, P, S.core.p, R->max_core, R, s);
             }
         }
     } catch (const KhError& e) {
@@ -1633,6 +1911,7 @@ void batch_chunk(kh_context* ctx, kh_graph* const* gs, int32_t count, const kh_p
         S.lid = PK.lid.p;
         S.seed = P->seed;
         S.stream_id = 0;
+        S.lazy = (P->flags & KH_LAZY_INIT) != 0;
         S.s = s;
         S.setup(nullptr);
         S.peel(nullptr);
@@ -1695,6 +1974,7 @@ extern "C" kh_status kh_core_batch(kh_context* ctx, int32_t count, kh_graph* con
     try {
         if (!ctx || count < 0 || (count > 0 && (!graphs || !core_outs))) fail(KH_EINVAL);
         if (count == 0) return KH_OK;
+        if ((P->flags & KH_WANT_DENSE) && (P->flags & KH_DENSE_FULL)) fail(KH_ENOTIMPL);
         for (int32_t i = 0; i < count; ++i) {
             check_params(graphs[i], P);
             if (graphs[i]->ctx != ctx) fail(KH_EINVAL);
@@ -1900,6 +2180,7 @@ extern "C" kh_status kh_dense(kh_graph* g, const kh_params* P, const int32_t* co
         check_params(g, P);
         if (!res || (g->n > 0 && !core_in)) fail(KH_EINVAL);
         clear_result(res);
+        if (P->flags & KH_DENSE_FULL) fail(KH_ENOTIMPL);  // the order comes from the peel itself
         if (g->n == 0) return KH_OK;
         hip_ok(hipSetDevice(g->ctx->device));
         StateLease lease(g->ctx);

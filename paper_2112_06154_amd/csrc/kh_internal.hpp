@@ -17,6 +17,9 @@ namespace kh {
 constexpr int kPullChunk = 128;
 // Arcs per chunk of the frontier-expansion kernels.
 constexpr int kExpandChunk = 256;
+// A hop of the R-mask BFS pulls (every alive vertex scans its neighbours) once
+// its frontier's arcs exceed 1 / kRbfsPullRatio of all arcs; below that it pushes.
+constexpr int kRbfsPullRatio = 4;
 // A BFS hop sweeps every work item once the previous frontier's adjacency
 // exceeds 1 / kSweepRatio of all arcs; below that it pulls only the alive
 // neighbours of the frontier.
@@ -69,6 +72,9 @@ struct RoundState {
     unsigned long long pull_bytes;   // algorithmic bytes of the pull kernel (without neighbour gathers)
     unsigned long long pull_gather;  // bytes of neighbour frontier words gathered by the pull kernel
     unsigned long long union_bytes;  // algorithmic bytes of the level >= 2 union kernel
+    unsigned long long rbfs_bytes;   // algorithmic bytes of the R-mask BFS hops (push and pull)
+    long long hop_arcs;              // arcs of the current R-mask BFS frontier (push/pull choice)
+    long long next_arcs;             // arcs of the frontier the current hop builds
 };
 
 // Optional HIP-event timing of every launch of a kernel, on the stream it is
@@ -99,16 +105,22 @@ void launch_alive_degree(const int32_t* rp, const int32_t* col, const uint8_t* a
                          hipStream_t s);
 void launch_compact_alive(const uint8_t* alive, int32_t n, int32_t* out, int* count, hipStream_t s);
 void launch_round_reset(RoundState* st, hipStream_t s, int gate = 0);
+// inexact (nullable): also st->min_inexact = min key over alive v with inexact[v] == 0
+// ("not exact": for the lazy top level, the vertices not yet active).
 void launch_reduce(const int64_t* key, const int64_t* val, const uint8_t* alive, int32_t n, RoundState* st,
-                   hipStream_t s, int gate = 0);
+                   hipStream_t s, int gate = 0, const uint8_t* exact = nullptr);
 void launch_round_begin(RoundState* st, int64_t* cand_k, int64_t* cand_size, int64_t* cand_sum, int early_stop,
                         hipStream_t s);
+// rnd (nullable): rnd[v] = the round's epoch for every vertex taken (its deletion round).
 void launch_select(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core, int32_t* rlist,
-                   int32_t* mark, int32_t epoch, int kill, hipStream_t s);
+                   int32_t* mark, int32_t epoch, int kill, hipStream_t s, int32_t* rnd = nullptr);
 void launch_kill_list(const int32_t* list, const int* count, uint8_t* alive, hipStream_t s);
 // Chunk queue over the adjacency of list[*lo .. *hi) (lo/hi may be NULL: 0 and count).
+// arcs (nullable): adds the listed vertices' degrees.  pull_st (nullable): does
+// nothing when that round state's mask-BFS hop pulls (see launch_rbfs_hop).
 void launch_enqueue(const int32_t* list, const int* lo, const int* hi, const int32_t* rp, int32_t* qv, int32_t* qb,
-                    int* qcount, hipStream_t s);
+                    int* qcount, hipStream_t s, long long* arcs = nullptr, const RoundState* pull_st = nullptr,
+                    int64_t nnz = -1);
 // mode 0: mark alive unmarked neighbours with `epoch` and append them to out[*out_count++]
 // mode 1: decrement adeg of alive neighbours
 void launch_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
@@ -143,12 +155,12 @@ void launch_unstall(RoundState* st, hipStream_t s);
 // when no inexact bound is at or below c' = max(c, min key) (then c = c',
 // rounds += 1, R = {key <= c}), else stall; mode 2 once nothing is alive.
 void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core,
-                          int32_t* rlist, int32_t* mark, hipStream_t s);
+                          int32_t* rlist, int32_t* mark, hipStream_t s, int32_t* rnd = nullptr);
 // For the listed R (rlist, *rcount): mode 0 sets R's mask bits (bit j for
 // rlist[j]) in rmask and gain, mode 1 removes R from the alive set; both then
 // queue R's adjacency in chunks for the next expansion (*qcount must be 0).
 void launch_enqueue_r(const int32_t* rlist, const int* rcount, const int32_t* rp, int32_t* qv, int32_t* qb, int* qcount,
-                      int mode, uint64_t* rmask, uint64_t* gain, uint8_t* alive, hipStream_t s);
+                      int mode, uint64_t* rmask, uint64_t* gain, uint8_t* alive, hipStream_t s, long long* arcs = nullptr);
 // Mask BFS bookkeeping of hop t: hopfill[t] = aff_fill, then the resets of hop
 // t + 1 (t < h) or the expansion queue (t == h).
 void launch_hop_end(RoundState* st, int* hopfill, int t, int h, hipStream_t s);
@@ -173,7 +185,17 @@ void launch_decide_seg(RoundState* st, int nseg, int* shist, long long* shi, int
 void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
                         const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
                         int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
-                        int32_t* alist, int* aff_fill, RoundState* st, hipStream_t s);
+                        int32_t* alist, int* aff_fill, RoundState* st, hipStream_t s, int64_t nnz = -1);
+// One hop of the R-mask BFS in push form (the frontier's chunks, as
+// launch_rbfs_expand) or, when the frontier's arcs exceed 1/kRbfsPullRatio of
+// all nnz arcs, in pull form (every alive vertex ORs the frontier masks of its
+// neighbours); both kernels are launched and the one not chosen returns at
+// once.  timer (nullable) brackets the pair as one launch.
+void launch_rbfs_hop(const int32_t* qv, const int32_t* qb, const int* qcount, int32_t n, const int32_t* rp,
+                     const int32_t* col, const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask,
+                     uint64_t* gain_next, int32_t* mark, int32_t* fmark, int32_t* fnext, int* fnext_count,
+                     int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz, hipStream_t s,
+                     PullTimer* timer = nullptr);
 void launch_clear_u64_list(const int32_t* list, const int* count, uint64_t* arr, hipStream_t s);
 // exact decrement for vertices at distance exactly h (deg -= |R within h|), bound otherwise
 void launch_decay_masked(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
@@ -289,13 +311,44 @@ void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount
 // Keep only the worklist vertices whose list can change.
 // hubs (nullable): vertices with more than kHubDegree neighbours that need a
 // re-merge go to this list instead of rc.
+// active (nullable): vertices with active[v] == 0 (not yet initialised at this
+// level) are never re-merged.
 void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int32_t* lostmax, int32_t* rc,
                      int* rc_count, hipStream_t s, const int32_t* rp = nullptr, int32_t* hubs = nullptr,
-                     int* hub_count = nullptr);
+                     int* hub_count = nullptr, const uint8_t* active = nullptr);
+// Lazy initialisation of level h (Sec. 5): d[v] = a lower bound on the estimate
+// from the level h-1 lists of v's alive neighbours (prev), for the inactive
+// vertices of the list (NULL: all); resets their lostmax.
+void launch_lazy_lb(const int32_t* list, const int* count, int32_t n, const int32_t* rp, const int32_t* col,
+                    const uint8_t* alive, const uint8_t* active, const uint8_t* rank, int32_t M, const int32_t* Mv,
+                    LevelView prev, int64_t* d, int32_t* lostmax, hipStream_t s);
+// stall = (some inactive bound <= c' = max(c, min d)), hi = 2 c' + 64, rc_count = 0
+void launch_lazy_decide(RoundState* st, hipStream_t s);
+// When stalled: out[rc_count++] = every alive inactive v with d[v] <= hi, now active.
+void launch_lazy_pick(const uint8_t* alive, uint8_t* active, const int64_t* d, int32_t n, RoundState* st,
+                      int32_t* out, hipStream_t s);
 // Alg. 1 estimate from level h.  worklist == NULL: all vertices.
 void launch_estimate(const int32_t* worklist, const int* wl_count, int32_t n, const uint8_t* alive,
                      const uint8_t* rank, const int32_t* size, const uint8_t* kk, int32_t M, const int32_t* Mv,
                      int64_t* d, RoundState* st, hipStream_t s);
+
+// ---- deletion order of the bulk-round peel (kh_order.hip) ------------------------------
+// Working arrays of deletion_order: n entries each, plus temp_bytes of sort storage.
+struct OrderScratch {
+    uint32_t* lkey;
+    uint32_t* lkey_out;
+    int32_t* ids;
+    int32_t* ids_out;
+    uint64_t* mkey;
+    uint64_t* mkey_out;
+    void* temp;
+    size_t temp_bytes;
+};
+size_t order_temp_bytes(int32_t n);
+// order[i] = i-th deleted vertex by (rnd[v], key[v], lev[v] (nullable: 0), v);
+// pos[order[i]] = i.  *bad |= 1 if some rnd < 0 or key outside [0, 2^32).
+hipError_t deletion_order(int32_t n, const int32_t* rnd, const int64_t* key, const uint8_t* lev, OrderScratch w,
+                          int32_t* order, int64_t* pos, int* bad, hipStream_t s);
 
 // ---- h-degrees in a fixed device array (kh_noalloc.hip) --------------------------------
 // Size of the array (per GPU, held until the process ends) and the most GPUs

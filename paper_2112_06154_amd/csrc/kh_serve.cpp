@@ -167,10 +167,14 @@ void worker(Server* S) {
             batch.push_back(head);
             est = head->est;
             int64_t vn = head->n;
-            if (!(head->p.flags & KH_EARLY_STOP)) {
+            if (!(head->p.flags & KH_EARLY_STOP) && !(head->p.flags & KH_DENSE_FULL)) {
                 for (auto it = S->queue.begin(); it != S->queue.end();) {
                     Request* r = *it;
-                    if (same_params(r->p, head->p) && vn + r->n <= S->batch_vertices &&
+                    // a packed batch finishes with its largest graph, so only
+                    // graphs within a factor 4 of the head's size join it: a
+                    // small request never waits for a large one
+                    const bool similar = 4 * r->n >= head->n && r->n <= 4 * head->n;
+                    if (similar && same_params(r->p, head->p) && vn + r->n <= S->batch_vertices &&
                         S->reserved + est + r->est <= S->budget) {
                         batch.push_back(r);
                         est += r->est;

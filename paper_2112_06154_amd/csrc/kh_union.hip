@@ -703,7 +703,8 @@ void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount
 // while a neighbour sits at level k; or (not cut, m = 0) always.
 __global__ void k_classify(const int32_t* __restrict__ wl, const int* wl_count, LevelView cur,
                            int32_t* __restrict__ lostmax, int32_t* __restrict__ rc, int* rc_count,
-                           const int32_t* __restrict__ rp, int32_t* __restrict__ hubs, int* hub_count) {
+                           const int32_t* __restrict__ rp, int32_t* __restrict__ hubs, int* hub_count,
+                           const uint8_t* __restrict__ active) {
     const int total = *wl_count;
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x; base < total; base += stride) {
@@ -712,12 +713,15 @@ __global__ void k_classify(const int32_t* __restrict__ wl, const int* wl_count, 
         int32_t v = 0;
         if (i < total) {
             v = wl[i];
-            const int k = cur.k[v];
-            const int L = lostmax[v];
-            lostmax[v] = -1;
-            if (cur.cut[v]) need = L >= k - 1;
-            else if (cur.m[v] > 0) need = L >= k;
-            else need = true;
+            if (!active || active[v]) {
+                // (inactive vertices of a lazily initialised level get a new bound instead)
+                const int k = cur.k[v];
+                const int L = lostmax[v];
+                lostmax[v] = -1;
+                if (cur.cut[v]) need = L >= k - 1;
+                else if (cur.m[v] > 0) need = L >= k;
+                else need = true;
+            }
         }
         const bool hub = need && hubs && rp[v + 1] - rp[v] > kHubDegree;
         const int slot = wave_append_slot(need && !hub, rc_count);
@@ -727,9 +731,107 @@ __global__ void k_classify(const int32_t* __restrict__ wl, const int* wl_count, 
     }
 }
 void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int32_t* lostmax, int32_t* rc,
-                     int* rc_count, hipStream_t s, const int32_t* rp, int32_t* hubs, int* hub_count) {
+                     int* rc_count, hipStream_t s, const int32_t* rp, int32_t* hubs, int* hub_count,
+                     const uint8_t* active) {
     hipLaunchKernelGGL(k_classify, dim3(1024), dim3(256), 0, s, wl, wl_count, cur, lostmax, rc, rc_count, rp, hubs,
-                       hub_count);
+                       hub_count, active);
+}
+
+// ---- lazy initialisation of the top level (Sec. 5, first heuristic) ---------------------
+// For alive v and an alive neighbour w, Y = N(w; h-1, X) lies inside N(v; h, X)
+// and contains v, so by Prop. monotone the estimate of the rank list
+// (r[v], ranks of Y \ {v}) is at most d(v).  Its level is k[w,h-1] (the
+// smallest k with |Y_{r>=k}| <= M, the closed form of the level) and its count
+// at that level is |B[w,h-1]| - [r[v] >= k[w,h-1]].  The largest such value over
+// the alive neighbours is a lower bound on d(v) that needs no list of v's own:
+// B[v,h] is built only once that bound no longer keeps v above the running
+// maximum.  Written to d[v] for the inactive vertices of the list (all
+// vertices when list == NULL); lostmax[v] is reset for them.
+__global__ void k_lazy_lb(const int32_t* __restrict__ list, const int* count, int32_t n,
+                          const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                          const uint8_t* __restrict__ alive, const uint8_t* __restrict__ active,
+                          const uint8_t* __restrict__ rank, int32_t M0, const int32_t* __restrict__ Mv,
+                          LevelView prev, int64_t* __restrict__ d, int32_t* __restrict__ lostmax) {
+    const int total = list ? *count : n;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int l = lane_id();
+    for (int i = wave; i < total; i += nwaves) {
+        const int32_t v = list ? list[i] : i;
+        if (!alive[v] || active[v]) continue;
+        const long long M = Mv ? Mv[v] : M0;
+        const int rv = rank[v];
+        long long lb = 0;
+        for (int32_t p = rp[v] + l; p < rp[v + 1]; p += 64) {
+            const int32_t w = col[p];
+            if (!alive[w]) continue;
+            const uint32_t mt = prev.meta[w];
+            const int k = (int)((mt >> 16) & 0xFFu);
+            const long long T = (long long)(mt & 0xFFFFu) - (rv >= k ? 1 : 0);
+            // levels this high only make the bound smaller than it could be: still a bound
+            const int kk = k < 40 ? k : 40;
+            long long e = T << kk;
+            if (kk > 0) {
+                const long long fl = M << (kk - 1);
+                e = fl > e ? fl : e;
+            }
+            lb = e > lb ? e : lb;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const long long t = __shfl_xor(lb, o);
+            lb = t > lb ? t : lb;
+        }
+        if (l == 0) {
+            d[v] = lb;
+            lostmax[v] = -1;
+        }
+    }
+}
+void launch_lazy_lb(const int32_t* list, const int* count, int32_t n, const int32_t* rp, const int32_t* col,
+                    const uint8_t* alive, const uint8_t* active, const uint8_t* rank, int32_t M, const int32_t* Mv,
+                    LevelView prev, int64_t* d, int32_t* lostmax, hipStream_t s) {
+    if (n <= 0) return;
+    const int grid = list ? 1024 : grid_for((int64_t)n * 64, 256, 16384);
+    hipLaunchKernelGGL(k_lazy_lb, dim3(grid), dim3(256), 0, s, list, count, n, rp, col, alive, active, rank, M, Mv,
+                       prev, d, lostmax);
+}
+
+// Activation round: when some inactive bound is at or below c' = max(c, min d),
+// the round stalls (no deletion) and every inactive vertex with bound <= 2 c' + 64
+// becomes active; its top-level list is then built from scratch.  (Activating
+// early only costs list upkeep; the slack keeps the number of stalled rounds
+// near the number of doublings of c instead of one per distinct bound.)
+__global__ void k_lazy_decide(RoundState* st) {
+    if (st->alive_count == 0) {
+        st->stall = 0;
+        return;
+    }
+    const long long c = st->min_key > st->c ? st->min_key : st->c;
+    st->stall = st->min_inexact <= c ? 1 : 0;
+    st->hi = c > (1ll << 60) ? c : 2 * c + 64;
+    st->rc_count = 0;
+}
+void launch_lazy_decide(RoundState* st, hipStream_t s) { hipLaunchKernelGGL(k_lazy_decide, dim3(1), dim3(1), 0, s, st); }
+
+__global__ void k_lazy_pick(const uint8_t* __restrict__ alive, uint8_t* __restrict__ active,
+                            const int64_t* __restrict__ d, int32_t n, RoundState* st, int32_t* __restrict__ out) {
+    if (!st->stall) return;
+    const long long hi = st->hi;
+    const int32_t stride = gridDim.x * blockDim.x;
+    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int32_t v = base + threadIdx.x;
+        const bool take = v < n && alive[v] && !active[v] && d[v] <= hi;
+        const int slot = wave_append_slot(take, &st->rc_count);
+        if (take) {
+            out[slot] = v;
+            active[v] = 1;
+        }
+    }
+}
+void launch_lazy_pick(const uint8_t* alive, uint8_t* active, const int64_t* d, int32_t n, RoundState* st,
+                      int32_t* out, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_lazy_pick, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, alive, active, d, n, st, out);
 }
 
 // ---- Alg. 1: d = |B[v,h] \ {v}| 2^k, and max(d, M 2^(k-1)) when k > 0 ---------------------------

@@ -34,6 +34,8 @@ KH_WANT_DENSE = 1
 KH_DENSE_PRUNE = 2
 KH_EARLY_STOP = 4
 KH_OUT_DEVICE = 8
+KH_DENSE_FULL = 16
+KH_LAZY_INIT = 32
 
 EXPORTED = [
     "kh_status_str", "kh_buffer_size", "kh_validate_csr", "kh_context_create", "kh_context_destroy",
@@ -189,11 +191,11 @@ class Context:
             self.handle = None
 
     def profile(self, on: bool) -> None:
-        """Start (resetting totals) or stop HIP-event timing of the h-degree pull kernel."""
+        """Start (resetting totals) or stop HIP-event timing of the instrumented kernels."""
         _check(lib().kh_profile_enable(self.handle, int(on)), "kh_profile_enable")
 
     def profile_read(self, kernel: int = 0) -> dict:
-        """Totals for kernel 0 (h-degree pull) or 1 (sample-list union)."""
+        """Totals for kernel 0 (h-degree pull), 1 (sample-list union) or 2 (R-mask BFS hop of the exact peel)."""
         la, by, ga = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         ms = ctypes.c_double()
         _check(lib().kh_profile_read(self.handle, kernel, ctypes.byref(la), ctypes.byref(ms), ctypes.byref(by),
@@ -260,9 +262,10 @@ class Graph:
 
 def make_params(h: int, epsilon: float = 0.0, delta: float = 0.05, seed: int = 0, M_override: int = 0,
                 M_dense_override: int = 0, dense: bool = False, prune: bool = False, early_stop: bool = False,
-                out_device: bool = False) -> Params:
-    flags = (KH_WANT_DENSE if dense else 0) | (KH_DENSE_PRUNE if prune else 0) | \
-            (KH_EARLY_STOP if early_stop else 0) | (KH_OUT_DEVICE if out_device else 0)
+                out_device: bool = False, dense_full: bool = False, lazy_init: bool = False) -> Params:
+    flags = (KH_WANT_DENSE if dense or dense_full else 0) | (KH_DENSE_PRUNE if prune else 0) | \
+            (KH_EARLY_STOP if early_stop else 0) | (KH_OUT_DEVICE if out_device else 0) | \
+            (KH_DENSE_FULL if dense_full else 0) | (KH_LAZY_INIT if lazy_init else 0)
     return Params(h, epsilon, delta, seed & 0xFFFFFFFFFFFFFFFF, M_override, M_dense_override, flags)
 
 
