@@ -170,8 +170,9 @@ kh_status kh_core(kh_graph *g, const kh_params *params, int32_t *core_out, kh_re
  *     KH_WANT_DENSE, the dense_* fields of that graph; rounds, edges_traversed,
  *     arcs_scanned, list_elements and seconds describe the packed union the
  *     graph was part of (equal across its graphs).
- * Unions hold at most 2^24 - 1 vertices (sampled) or 2^31 - 2 vertices and
- * 2^31 - 1 arcs (exact); larger batches run as consecutive unions.
+ * Graphs are packed by size: a union holds graphs within a factor 4 of its
+ * smallest one, and at most 2^24 - 1 vertices (sampled) or 2^31 - 2 vertices and
+ * 2^31 - 1 arcs (exact); a batch runs as consecutive unions.
  * Errors: as kh_core; KH_ENOTIMPL with KH_EARLY_STOP (its stopping test is per
  * graph).  On error no result of the batch is valid. */
 kh_status kh_core_batch(kh_context *ctx, int32_t count, kh_graph *const *graphs, const kh_params *params,

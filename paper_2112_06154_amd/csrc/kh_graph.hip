@@ -731,7 +731,7 @@ __global__ void k_bound_hist(const uint8_t* __restrict__ alive, const int64_t* _
 void launch_bound_hist(const uint8_t* alive, const int64_t* deg, const uint8_t* exact, int32_t n, RoundState* st,
                        hipStream_t s, const int32_t* seg, int* shist, int gate) {
     if (n > 0)
-        hipLaunchKernelGGL(k_bound_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, alive, deg, exact, n, st, seg,
+        hipLaunchKernelGGL(k_bound_hist, dim3(grid_for(n, 256, 256)), dim3(256), 0, s, alive, deg, exact, n, st, seg,
                            shist, gate);
 }
 
@@ -856,7 +856,9 @@ __global__ __launch_bounds__(256) void k_reduce_hist(const int64_t* __restrict__
 void launch_reduce_hist(const int64_t* deg, const uint8_t* alive, const uint8_t* exact, int32_t n, RoundState* st,
                         hipStream_t s) {
     if (n > 0)
-        hipLaunchKernelGGL(k_reduce_hist, dim3(grid_for((n + 3) / 4, 256, 4096)), dim3(256), 0, s, deg, alive, exact,
+        // one block per CU: each block adds three values into one cache line of
+        // the round state, and those atomics queue up behind each other
+        hipLaunchKernelGGL(k_reduce_hist, dim3(grid_for((n + 3) / 4, 256, 256)), dim3(256), 0, s, deg, alive, exact,
                            n, st);
 }
 __global__ void k_unstall(RoundState* st) {
@@ -970,127 +972,115 @@ __device__ __forceinline__ void rbfs_count(unsigned long long bytes, long long n
     }
 }
 
-__global__ void k_rbfs_expand(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
-                              const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                              const uint8_t* __restrict__ alive, const uint64_t* __restrict__ gain_cur,
-                              uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain_next, int32_t* __restrict__ mark,
-                              int32_t epoch, int32_t* __restrict__ fmark, int32_t fepoch, int32_t* __restrict__ fnext,
-                              int* fnext_count, int32_t* __restrict__ alist, int* aff_fill, RoundState* st,
-                              int64_t nnz) {
-    if (rbfs_pulls(st, nnz)) return;  // the pull kernel takes this hop
-    if (epoch < 0) epoch = st->epoch;
-    if (fepoch < 0) fepoch = st->fepoch;
-    const int nq = *qcount;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    const int l = lane_id();
+// One hop of the mask BFS, in either form, chosen on the device (rbfs_pulls).
+// Push: a wave per 256-arc chunk of the frontier; every new bit of an alive
+// neighbour is or-ed into its mask with an atomic, and a vertex that gains one
+// joins the next frontier (fmark dedups) and, the first time in the round, the
+// affected list (mark).  Pull: vertex w gets new =
+// (OR over alive neighbours u of gain_cur[u]) & ~rmask[w] -- the union of what
+// the frontier would push to it (gain_cur is zero off the frontier and on
+// deleted vertices, which never carry bits).  One thread owns w, so no atomics;
+// the scan of w's arcs stops once w holds every bit of R (full), which for the
+// one- and two-vertex deletions of a long peel is usually after the first
+// frontier neighbour.
+__global__ __launch_bounds__(256) void k_rbfs_hop(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb,
+                                                  const int* qcount, int32_t n, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const uint8_t* __restrict__ alive,
+                                                  const uint64_t* __restrict__ gain_cur,
+                                                  uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain_next,
+                                                  int32_t* __restrict__ mark, int32_t* __restrict__ fmark,
+                                                  int32_t* __restrict__ fnext, int* fnext_count,
+                                                  int32_t* __restrict__ alist, int* aff_fill, RoundState* st,
+                                                  int64_t nnz) {
+    const int32_t epoch = st->epoch;
     unsigned long long bytes = 0;
     long long next_arcs = 0;
-    for (int q = wave; q < nq; q += nwaves) {
-        const int32_t u = qv[q];
-        const int32_t b = qb[q];
-        const int32_t e = min(b + kExpandChunk, rp[u + 1]);
-        const uint64_t g = gain_cur[u];
-        if (l == 0) bytes += 20;  // chunk (u, b), rp[u + 1], gain[u]
-        for (int32_t p0 = b; p0 < e; p0 += 64) {
-            const int32_t p = p0 + l;
-            bool want_f = false, want_a = false;
-            int32_t w = 0;
-            if (p < e && g) {
-                w = col[p];
-                bytes += 5;  // id, alive
+    if (!rbfs_pulls(st, nnz)) {
+        const int32_t fepoch = st->fepoch;
+        const int nq = *qcount;
+        const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+        const int nwaves = (gridDim.x * blockDim.x) >> 6;
+        const int l = lane_id();
+        for (int q = wave; q < nq; q += nwaves) {
+            const int32_t u = qv[q];
+            const int32_t b = qb[q];
+            const int32_t e = min(b + kExpandChunk, rp[u + 1]);
+            const uint64_t g = gain_cur[u];
+            if (l == 0) bytes += 20;  // chunk (u, b), rp[u + 1], gain[u]
+            for (int32_t p0 = b; p0 < e; p0 += 64) {
+                const int32_t p = p0 + l;
+                bool want_f = false, want_a = false;
+                int32_t w = 0;
+                if (p < e && g) {
+                    w = col[p];
+                    bytes += 5;  // id, alive
+                    if (alive[w]) {
+                        bytes += 8;  // rmask
+                        const uint64_t nb = g & ~rmask[w];
+                        if (nb) {
+                            const uint64_t old = atomicOr((unsigned long long*)&rmask[w], (unsigned long long)nb);
+                            const uint64_t nw = nb & ~old;
+                            if (nw) {
+                                bytes += 16;  // rmask, gain written
+                                atomicOr((unsigned long long*)&gain_next[w], (unsigned long long)nw);
+                                if (fmark[w] != fepoch) want_f = atomicExch(&fmark[w], fepoch) != fepoch;
+                                if (mark[w] != epoch) want_a = atomicExch(&mark[w], epoch) != epoch;
+                            }
+                        }
+                    }
+                }
+                const int sf = wave_append_slot(want_f, fnext_count);
+                if (want_f) {
+                    fnext[sf] = w;
+                    next_arcs += rp[w + 1] - rp[w];
+                }
+                const int sa = wave_append_slot(want_a, aff_fill);
+                if (want_a) alist[sa] = w;
+                bytes += (want_f ? 12 : 0) + (want_a ? 4 : 0);
+            }
+        }
+    } else {
+        const int rc = st->rcount;
+        const uint64_t full = rc >= 64 ? ~0ull : ((1ull << rc) - 1ull);
+        const int32_t stride = gridDim.x * blockDim.x;
+        for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+            const int32_t w = base + threadIdx.x;
+            bool front = false, first = false;
+            if (w < n) {
+                bytes += 1;
                 if (alive[w]) {
-                    bytes += 8;  // rmask
-                    const uint64_t nb = g & ~rmask[w];
-                    if (nb) {
-                        const uint64_t old = atomicOr((unsigned long long*)&rmask[w], (unsigned long long)nb);
-                        const uint64_t nw = nb & ~old;
+                    const uint64_t have = rmask[w];
+                    bytes += 8;
+                    if (have != full) {
+                        const int32_t b = rp[w], e = rp[w + 1];
+                        bytes += 8;
+                        uint64_t acc = 0ull;
+                        int32_t p = b;
+                        while (p < e) {
+                            acc |= gain_cur[col[p++]];
+                            if ((acc | have) == full) break;
+                        }
+                        bytes += 12ull * (unsigned long long)(p - b);  // ids and the neighbours' masks read
+                        const uint64_t nw = acc & ~have;
                         if (nw) {
-                            bytes += 16;  // rmask, gain written
-                            atomicOr((unsigned long long*)&gain_next[w], (unsigned long long)nw);
-                            if (fmark[w] != fepoch) want_f = atomicExch(&fmark[w], fepoch) != fepoch;
-                            if (mark[w] != epoch) want_a = atomicExch(&mark[w], epoch) != epoch;
+                            rmask[w] = have | nw;
+                            gain_next[w] = nw;
+                            front = true;
+                            next_arcs += e - b;
+                            first = mark[w] != epoch;
+                            if (first) mark[w] = epoch;
+                            bytes += 20;
                         }
                     }
                 }
             }
-            const int sf = wave_append_slot(want_f, fnext_count);
-            if (want_f) {
-                fnext[sf] = w;
-                next_arcs += rp[w + 1] - rp[w];
-            }
-            const int sa = wave_append_slot(want_a, aff_fill);
-            if (want_a) alist[sa] = w;
-            bytes += (want_f ? 12 : 0) + (want_a ? 4 : 0);
+            const int sf = wave_append_slot(front, fnext_count);
+            if (front) fnext[sf] = w;
+            const int sa = wave_append_slot(first, aff_fill);
+            if (first) alist[sa] = w;
+            bytes += (front ? 4 : 0) + (first ? 4 : 0);
         }
-    }
-    rbfs_count(bytes, next_arcs, st);
-}
-void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
-                        const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
-                        int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
-                        int32_t* alist, int* aff_fill, RoundState* st, hipStream_t s, int64_t nnz) {
-    hipLaunchKernelGGL(k_rbfs_expand, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, gain_cur, rmask,
-                       gain_next, mark, epoch, fmark, fepoch, fnext, fnext_count, alist, aff_fill, st, nnz);
-}
-
-// Pull form of a hop: vertex w gets new = (OR over alive neighbours u of
-// gain_cur[u]) & ~rmask[w] -- the union of what the frontier would push to it
-// (gain_cur is zero off the frontier and on deleted vertices, which never carry
-// bits).  One thread owns w, so no atomics; the scan of w's arcs stops once w
-// holds every bit of R (full), which for the one- and two-vertex deletions of a
-// long peel is usually after the first frontier neighbour.
-__global__ __launch_bounds__(256) void k_rbfs_pull(int32_t n, const int32_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ col,
-                                                   const uint8_t* __restrict__ alive,
-                                                   const uint64_t* __restrict__ gain_cur,
-                                                   uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain_next,
-                                                   int32_t* __restrict__ mark, int32_t* __restrict__ fnext,
-                                                   int* fnext_count, int32_t* __restrict__ alist, int* aff_fill,
-                                                   RoundState* st, int64_t nnz) {
-    if (!rbfs_pulls(st, nnz)) return;
-    const int32_t epoch = st->epoch;
-    const int rc = st->rcount;
-    const uint64_t full = rc >= 64 ? ~0ull : ((1ull << rc) - 1ull);
-    unsigned long long bytes = 0;
-    long long next_arcs = 0;
-    const int32_t stride = gridDim.x * blockDim.x;
-    for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const int32_t w = base + threadIdx.x;
-        bool front = false, first = false;
-        if (w < n) {
-            bytes += 1;
-            if (alive[w]) {
-                const uint64_t have = rmask[w];
-                bytes += 8;
-                if (have != full) {
-                    const int32_t b = rp[w], e = rp[w + 1];
-                    bytes += 8;
-                    uint64_t acc = 0ull;
-                    int32_t p = b;
-                    while (p < e) {
-                        acc |= gain_cur[col[p++]];
-                        if ((acc | have) == full) break;
-                    }
-                    bytes += 12ull * (unsigned long long)(p - b);  // ids and the neighbours' masks read
-                    const uint64_t nw = acc & ~have;
-                    if (nw) {
-                        rmask[w] = have | nw;
-                        gain_next[w] = nw;
-                        front = true;
-                        next_arcs += e - b;
-                        first = mark[w] != epoch;
-                        if (first) mark[w] = epoch;
-                        bytes += 20;
-                    }
-                }
-            }
-        }
-        const int sf = wave_append_slot(front, fnext_count);
-        if (front) fnext[sf] = w;
-        const int sa = wave_append_slot(first, aff_fill);
-        if (first) alist[sa] = w;
-        bytes += (front ? 4 : 0) + (first ? 4 : 0);
     }
     rbfs_count(bytes, next_arcs, st);
 }
@@ -1101,30 +1091,45 @@ void launch_rbfs_hop(const int32_t* qv, const int32_t* qb, const int* qcount, in
                      int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz, hipStream_t s, PullTimer* timer) {
     const bool timed = timer && timer->used < timer->cap;
     if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
-    hipLaunchKernelGGL(k_rbfs_expand, dim3(2048), dim3(256), 0, s, qv, qb, qcount, rp, col, alive, gain_cur, rmask,
-                       gain_next, mark, -1, fmark, -1, fnext, fnext_count, alist, aff_fill, st, nnz);
-    if (n > 0)
-        hipLaunchKernelGGL(k_rbfs_pull, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, n, rp, col, alive, gain_cur,
-                           rmask, gain_next, mark, fnext, fnext_count, alist, aff_fill, st, nnz);
+    hipLaunchKernelGGL(k_rbfs_hop, dim3(2048), dim3(256), 0, s, qv, qb, qcount, n, rp, col, alive, gain_cur, rmask,
+                       gain_next, mark, fmark, fnext, fnext_count, alist, aff_fill, st, nnz);
     if (timed) {
         (void)hipEventRecord(timer->ev[2 * timer->used + 1], s);
         timer->used += 1;
     }
 }
 
-__global__ void k_hop_end(RoundState* st, int* hopfill, int t, int h) {
-    hopfill[t] = st->aff_fill;
-    st->qcount = 0;
-    st->hop_arcs = st->next_arcs;  // the next hop's frontier
-    st->next_arcs = 0;
-    if (t < h) {
-        st->fepoch += 1;
-        st->fcount[(t + 1) & 1] = 0;
+// Zero arr[list[i]] for the previous frontier, then (last block) end hop t:
+// record the affected count reached (hopfill[t]), reset the chunk queue, take
+// the next frontier's arcs and clear its list fill.  Every block has read the
+// list's count before it is counted, and the end of the hop touches nothing the
+// blocks write.
+__global__ void k_clear_hop_end(const int32_t* __restrict__ list, const int* count, uint64_t* __restrict__ arr,
+                                RoundState* st, int* hopfill, int t, int h) {
+    const int cnt = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) arr[list[i]] = 0ull;
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(&st->blocks_done, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        st->blocks_done = 0;
+        hopfill[t] = st->aff_fill;
+        if (t < 4) st->hop_log[t] = st->hop_arcs;
+        st->qcount = 0;
+        st->hop_arcs = st->next_arcs;
+        st->next_arcs = 0;
+        if (t < h) {
+            st->fepoch += 1;
+            st->fcount[(t + 1) & 1] = 0;
+        }
     }
 }
-void launch_hop_end(RoundState* st, int* hopfill, int t, int h, hipStream_t s) {
-    hipLaunchKernelGGL(k_hop_end, dim3(1), dim3(1), 0, s, st, hopfill, t, h);
+void launch_clear_hop_end(const int32_t* list, const int* count, uint64_t* arr, RoundState* st, int* hopfill, int t,
+                          int h, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_hop_end, dim3(512), dim3(256), 0, s, list, count, arr, st, hopfill, t, h);
 }
+
 
 __global__ void k_clear_u64_lists3(const int32_t* __restrict__ l0, const int* c0, uint64_t* __restrict__ a0,
                                    const int32_t* __restrict__ l1, const int* c1, uint64_t* __restrict__ a1,
@@ -1155,13 +1160,6 @@ void launch_clear_u64_lists3(const int32_t* l0, const int* c0, uint64_t* a0, con
     hipLaunchKernelGGL(k_clear_u64_lists3, dim3(512), dim3(256), 0, s, l0, c0, a0, l1, c1, a1, l2, c2, a2, st);
 }
 
-__global__ void k_clear_u64_list(const int32_t* __restrict__ list, const int* count, uint64_t* __restrict__ arr) {
-    const int cnt = *count;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) arr[list[i]] = 0ull;
-}
-void launch_clear_u64_list(const int32_t* list, const int* count, uint64_t* arr, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_u64_list, dim3(512), dim3(256), 0, s, list, count, arr);
-}
 
 __global__ void k_decay_masked(const int32_t* __restrict__ alist, RoundState* st, const int* __restrict__ hopfill,
                                int h, const uint8_t* __restrict__ alive, const int32_t* __restrict__ adeg,

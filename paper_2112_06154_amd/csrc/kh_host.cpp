@@ -1023,8 +1023,7 @@ struct ExactRun {
             launch_rbfs_hop(qv.p, qb.p, &st.p->qcount, g->n, g->rp, g->col, alive.p, gain[(t - 1) & 1], rmask.p,
                             gain[t & 1], mark.p, fmark.p, fl[t & 1], &st.p->fcount[t & 1], alist.p, &st.p->aff_fill,
                             st.p, g->nnz, s, rt);
-            launch_clear_u64_list(src, srcn, gain[(t - 1) & 1], s);
-            launch_hop_end(st.p, hopfill.p, t, h, s);
+            launch_clear_hop_end(src, srcn, gain[(t - 1) & 1], st.p, hopfill.p, t, h, s);
         }
         // R leaves X and its chunks are queued (hop_end of hop h zeroed qcount);
         // the alive degrees drop
@@ -1034,9 +1033,11 @@ struct ExactRun {
 
     void trace_round(const RoundState& hs, const char* what, Clock::time_point t0) {
         if (trace_on() && (hs.rounds < 8 || (hs.rounds & 63) == 0))
-            std::fprintf(stderr, "[kh exact] %s round %d c %lld alive %d removed %d affected %d recomputed %lld t %.3fs\n",
-                         what, hs.rounds, hs.c, hs.alive_count, hs.rcount, hs.aff_fill, recomputed,
-                         std::chrono::duration<double>(Clock::now() - t0).count());
+            std::fprintf(stderr,
+                         "[kh exact] %s round %d c %lld alive %d removed %d affected %d hop arcs %lld %lld %lld "
+                         "recomputed %lld t %.3fs\n",
+                         what, hs.rounds, hs.c, hs.alive_count, hs.rcount, hs.aff_fill, hs.hop_log[1], hs.hop_log[2],
+                         hs.hop_log[3], recomputed, std::chrono::duration<double>(Clock::now() - t0).count());
     }
 
     // ExactCore with lazy degrees: deg[v] is either exact (exact[v] = 1) or a
@@ -2010,11 +2011,22 @@ extern "C" kh_status kh_core_batch(kh_context* ctx, int32_t count, kh_graph* con
             ci.clear();
             vn = an = 0;
         };
+        // A union's peel runs until its last graph is done and every round
+        // sweeps the whole union, while its rounds follow the distinct core values
+        // of all its graphs: so graphs are packed by size, each union holding
+        // graphs within a factor 4 of its smallest one.
+        std::vector<int32_t> idx;
         for (int32_t i = 0; i < count; ++i) {
+            if (graphs[i]->n == 0) continue;
+            if (sampled && graphs[i]->n > kMaxSampledN) fail(KH_ENOTIMPL);
+            idx.push_back(i);
+        }
+        std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return graphs[a]->n < graphs[b]->n; });
+        int64_t first_n = 0;
+        for (int32_t i : idx) {
             kh_graph* g = graphs[i];
-            if (g->n == 0) continue;
-            if (sampled && g->n > kMaxSampledN) fail(KH_ENOTIMPL);
-            if (vn + g->n > vmax || an + g->nnz > (int64_t)INT32_MAX) flush();
+            if (vn + g->n > vmax || an + g->nnz > (int64_t)INT32_MAX || (!cg.empty() && g->n > 4 * first_n)) flush();
+            if (cg.empty()) first_n = g->n;
             cg.push_back(g);
             co.push_back(core_outs[i]);
             ci.push_back(i);

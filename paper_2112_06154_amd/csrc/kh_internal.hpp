@@ -19,7 +19,7 @@ constexpr int kPullChunk = 128;
 constexpr int kExpandChunk = 256;
 // A hop of the R-mask BFS pulls (every alive vertex scans its neighbours) once
 // its frontier's arcs exceed 1 / kRbfsPullRatio of all arcs; below that it pushes.
-constexpr int kRbfsPullRatio = 4;
+constexpr int kRbfsPullRatio = 32;
 // A BFS hop sweeps every work item once the previous frontier's adjacency
 // exceeds 1 / kSweepRatio of all arcs; below that it pulls only the alive
 // neighbours of the frontier.
@@ -75,6 +75,7 @@ struct RoundState {
     unsigned long long rbfs_bytes;   // algorithmic bytes of the R-mask BFS hops (push and pull)
     long long hop_arcs;              // arcs of the current R-mask BFS frontier (push/pull choice)
     long long next_arcs;             // arcs of the frontier the current hop builds
+    long long hop_log[4];            // trace: frontier arcs of mask-BFS hops 1..3 of the last round
 };
 
 // Optional HIP-event timing of every launch of a kernel, on the stream it is
@@ -161,9 +162,11 @@ void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundSt
 // queue R's adjacency in chunks for the next expansion (*qcount must be 0).
 void launch_enqueue_r(const int32_t* rlist, const int* rcount, const int32_t* rp, int32_t* qv, int32_t* qb, int* qcount,
                       int mode, uint64_t* rmask, uint64_t* gain, uint8_t* alive, hipStream_t s, long long* arcs = nullptr);
-// Mask BFS bookkeeping of hop t: hopfill[t] = aff_fill, then the resets of hop
-// t + 1 (t < h) or the expansion queue (t == h).
-void launch_hop_end(RoundState* st, int* hopfill, int t, int h, hipStream_t s);
+// arr[list[i]] = 0 for i < *count, then end mask-BFS hop t: hopfill[t] =
+// aff_fill, qcount = 0, hop_arcs = next_arcs (next_arcs = 0), and for t < h a
+// new frontier epoch and fcount[(t+1)&1] = 0.
+void launch_clear_hop_end(const int32_t* list, const int* count, uint64_t* arr, RoundState* st, int* hopfill, int t,
+                          int h, hipStream_t s);
 // arr_k[list_k[i]] = 0 for three (list, count, array) triples at once; with
 // st != NULL the last block then resets the round state for the next round
 // (unless the sequence is stalled).
@@ -182,21 +185,15 @@ void launch_pick(const uint8_t* alive, const int64_t* deg, const uint8_t* exact,
 void launch_decide_seg(RoundState* st, int nseg, int* shist, long long* shi, int cap, hipStream_t s);
 // R-mask BFS: after h hops rmask[v] holds bit (j mod 64) for every deleted r_j within
 // distance h of v in G[X]; first-visited vertices are appended to alist in hop order.
-void launch_rbfs_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
-                        const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask, uint64_t* gain_next,
-                        int32_t* mark, int32_t epoch, int32_t* fmark, int32_t fepoch, int32_t* fnext, int* fnext_count,
-                        int32_t* alist, int* aff_fill, RoundState* st, hipStream_t s, int64_t nnz = -1);
-// One hop of the R-mask BFS in push form (the frontier's chunks, as
-// launch_rbfs_expand) or, when the frontier's arcs exceed 1/kRbfsPullRatio of
-// all nnz arcs, in pull form (every alive vertex ORs the frontier masks of its
-// neighbours); both kernels are launched and the one not chosen returns at
-// once.  timer (nullable) brackets the pair as one launch.
+// One hop, in push form (the frontier's chunks queued by launch_enqueue_r /
+// launch_enqueue) or, when the frontier's arcs exceed 1/kRbfsPullRatio of all
+// nnz arcs, in pull form (every alive vertex ORs the frontier masks of its
+// neighbours), decided inside the one kernel.  timer (nullable) brackets it.
 void launch_rbfs_hop(const int32_t* qv, const int32_t* qb, const int* qcount, int32_t n, const int32_t* rp,
                      const int32_t* col, const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask,
                      uint64_t* gain_next, int32_t* mark, int32_t* fmark, int32_t* fnext, int* fnext_count,
                      int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz, hipStream_t s,
                      PullTimer* timer = nullptr);
-void launch_clear_u64_list(const int32_t* list, const int* count, uint64_t* arr, hipStream_t s);
 // exact decrement for vertices at distance exactly h (deg -= |R within h|), bound otherwise
 void launch_decay_masked(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
                          const int32_t* adeg, const int32_t* anchor, const uint64_t* rmask, int64_t* deg,
