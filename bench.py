@@ -70,7 +70,7 @@ def measured_traffic(k, stages, hs):
 # are merged by a second, wider variant inside the same timed launch)
 KERNEL_NAMES = {0: ["k_ms_pull<16>", "k_ms_pull<8>", "k_ms_pull<4>", "k_ms_pull<2>", "k_ms_pull<1>"],
                 1: ["k_union<256>", "k_union<1024>"],
-                2: ["k_rbfs_expand", "k_rbfs_pull"]}
+                2: ["k_rbfs_hop"]}
 # FETCH_SIZE reads 524,317 KiB for the 1 GiB read by the add kernel of
 # --copy-calib, WRITE_SIZE 1,048,576 KiB for its 1 GiB write
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
@@ -634,7 +634,7 @@ def main():
     ctx.profile(False)
 
     names = ["k_ms_pull (bit-parallel h-degree pull hop)", "k_union (sample-list union, levels >= 2)",
-             "k_rbfs_expand / k_rbfs_pull (exact peel: one hop of the deleted set's mask BFS)"]
+             "k_rbfs_hop (exact peel: one push or pull hop of the deleted set's mask BFS)"]
 
     def roofline(k):
         p = profs[k]

@@ -394,8 +394,8 @@ void launch_enqueue(const int32_t* list, const int* lo, const int* hi, const int
 
 __global__ void k_enqueue_r(const int32_t* __restrict__ rlist, const int* rcount, const int32_t* __restrict__ rp,
                             int32_t* __restrict__ qv, int32_t* __restrict__ qb, int* qcount, int mode,
-                            uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain, uint8_t* __restrict__ alive,
-                            long long* arcs) {
+                            uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain, uint32_t* __restrict__ fbits,
+                            uint8_t* __restrict__ alive, long long* arcs) {
     const int hi = *rcount;
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x; base < hi; base += stride) {
@@ -407,6 +407,7 @@ __global__ void k_enqueue_r(const int32_t* __restrict__ rlist, const int* rcount
                 const unsigned long long b = 1ull << (i & 63);
                 atomicOr((unsigned long long*)&rmask[v], b);
                 atomicOr((unsigned long long*)&gain[v], b);
+                atomicOr(&fbits[v >> 5], 1u << (v & 31));
             } else {
                 alive[v] = 0;
             }
@@ -430,9 +431,10 @@ __global__ void k_enqueue_r(const int32_t* __restrict__ rlist, const int* rcount
     }
 }
 void launch_enqueue_r(const int32_t* rlist, const int* rcount, const int32_t* rp, int32_t* qv, int32_t* qb, int* qcount,
-                      int mode, uint64_t* rmask, uint64_t* gain, uint8_t* alive, hipStream_t s, long long* arcs) {
+                      int mode, uint64_t* rmask, uint64_t* gain, uint32_t* fbits, uint8_t* alive, hipStream_t s,
+                      long long* arcs) {
     hipLaunchKernelGGL(k_enqueue_r, dim3(256), dim3(256), 0, s, rlist, rcount, rp, qv, qb, qcount, mode, rmask, gain,
-                       alive, arcs);
+                       fbits, alive, arcs);
 }
 
 __global__ void k_expand(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb, const int* qcount,
@@ -973,43 +975,107 @@ __device__ __forceinline__ void rbfs_count(unsigned long long bytes, long long n
 }
 
 // One hop of the mask BFS, in either form, chosen on the device (rbfs_pulls).
+// The frontier is held twice: gain (the bits each frontier vertex passes on,
+// zero elsewhere) and a one-bit-per-vertex bitmap fbits (n/8 bytes, resident in
+// L2), so that a neighbour off the frontier costs a bit test, not an 8-byte
+// gather.  fbits_next is null at the last hop, whose frontier is never read.
 // Push: a wave per 256-arc chunk of the frontier; every new bit of an alive
 // neighbour is or-ed into its mask with an atomic, and a vertex that gains one
 // joins the next frontier (fmark dedups) and, the first time in the round, the
 // affected list (mark).  Pull: vertex w gets new =
 // (OR over alive neighbours u of gain_cur[u]) & ~rmask[w] -- the union of what
 // the frontier would push to it (gain_cur is zero off the frontier and on
-// deleted vertices, which never carry bits).  One thread owns w, so no atomics;
-// the scan of w's arcs stops once w holds every bit of R (full), which for the
-// one- and two-vertex deletions of a long peel is usually after the first
-// frontier neighbour.
+// deleted vertices, which never carry bits); the scan of w's arcs stops once w
+// holds every bit of R (full), which for the one- and two-vertex deletions of a
+// long peel is usually at the first frontier neighbour.  A thread owns a vertex
+// of at most kRbfsLight arcs and scans four arcs per step; the arcs of a larger
+// vertex are scanned by its whole wave, 64 at a time.
+__device__ __forceinline__ bool fbit(const uint32_t* __restrict__ fbits, int32_t x) {
+    return (fbits[x >> 5] >> (x & 31)) & 1u;
+}
+
+// The hop's two output lists (next frontier, affected) are gathered per block in
+// LDS and copied out with one global atomic per flush: a device-wide counter
+// hit once per wave step serialises (about 6 ns per atomic, so the 20,000
+// appends of a 600,000-arc hop cost more than the hop's own work).
+constexpr int kRbfsBuf = 2048;
+
+__device__ __forceinline__ void lds_append(bool want, int32_t v, int32_t* buf, int* n) {
+    const unsigned long long m = __ballot(want);
+    if (m == 0ull) return;
+    const int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(n, __popcll(m));
+    base = __shfl(base, leader);
+    if (want) buf[base + __popcll(m & ((1ull << lane_id()) - 1ull))] = v;
+}
+
+// Block-uniform (every thread calls it after a barrier): copies the buffered
+// entries to out[*count ...] and empties the buffer.
+__device__ __forceinline__ void lds_flush(int32_t* buf, int* n, int* gbase, int32_t* __restrict__ out, int* count) {
+    const int cnt = *n;
+    if (cnt == 0) return;
+    if (threadIdx.x == 0) *gbase = atomicAdd(count, cnt);
+    __syncthreads();
+    const int base = *gbase;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) out[base + i] = buf[i];
+    __syncthreads();
+    if (threadIdx.x == 0) *n = 0;
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_rbfs_hop(const int32_t* __restrict__ qv, const int32_t* __restrict__ qb,
                                                   const int* qcount, int32_t n, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col,
                                                   const uint8_t* __restrict__ alive,
                                                   const uint64_t* __restrict__ gain_cur,
+                                                  const uint32_t* __restrict__ fbits_cur,
                                                   uint64_t* __restrict__ rmask, uint64_t* __restrict__ gain_next,
+                                                  uint32_t* __restrict__ fbits_next,
                                                   int32_t* __restrict__ mark, int32_t* __restrict__ fmark,
                                                   int32_t* __restrict__ fnext, int* fnext_count,
                                                   int32_t* __restrict__ alist, int* aff_fill, RoundState* st,
                                                   int64_t nnz) {
     const int32_t epoch = st->epoch;
+    const int l = lane_id();
     unsigned long long bytes = 0;
     long long next_arcs = 0;
+    __shared__ int32_t s_f[kRbfsBuf], s_a[kRbfsBuf];
+    __shared__ int s_nf, s_na, s_gb;
+    if (threadIdx.x == 0) {
+        s_nf = 0;
+        s_na = 0;
+    }
+    __syncthreads();
+    // after each block-wide step: flush a buffer that could not take another
+    // step's worth of entries
+    auto maybe_flush = [&]() {
+        __syncthreads();
+        const bool ff = s_nf > kRbfsBuf - 256, fa = s_na > kRbfsBuf - 256;
+        __syncthreads();
+        if (ff) lds_flush(s_f, &s_nf, &s_gb, fnext, fnext_count);
+        if (fa) lds_flush(s_a, &s_na, &s_gb, alist, aff_fill);
+    };
     if (!rbfs_pulls(st, nnz)) {
         const int32_t fepoch = st->fepoch;
         const int nq = *qcount;
-        const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-        const int nwaves = (gridDim.x * blockDim.x) >> 6;
-        const int l = lane_id();
-        for (int q = wave; q < nq; q += nwaves) {
-            const int32_t u = qv[q];
-            const int32_t b = qb[q];
-            const int32_t e = min(b + kExpandChunk, rp[u + 1]);
-            const uint64_t g = gain_cur[u];
-            if (l == 0) bytes += 20;  // chunk (u, b), rp[u + 1], gain[u]
-            for (int32_t p0 = b; p0 < e; p0 += 64) {
-                const int32_t p = p0 + l;
+        const int wpb = blockDim.x >> 6;
+        const int wib = threadIdx.x >> 6;
+        // the block takes wpb chunks at a time (one per wave), so that every
+        // thread runs the same number of steps
+        for (int qg = blockIdx.x * wpb; qg < nq; qg += gridDim.x * wpb) {
+            const int q = qg + wib;
+            int32_t b = 0, e = 0;
+            uint64_t g = 0ull;
+            if (q < nq) {
+                const int32_t u = qv[q];
+                b = qb[q];
+                e = min(b + kExpandChunk, rp[u + 1]);
+                g = gain_cur[u];
+                if (l == 0) bytes += 20;  // chunk (u, b), rp[u + 1], gain[u]
+            }
+            for (int step = 0; step < kExpandChunk; step += 64) {
+                const int32_t p = b + step + l;
                 bool want_f = false, want_a = false;
                 int32_t w = 0;
                 if (p < e && g) {
@@ -1030,84 +1096,162 @@ __global__ __launch_bounds__(256) void k_rbfs_hop(const int32_t* __restrict__ qv
                         }
                     }
                 }
-                const int sf = wave_append_slot(want_f, fnext_count);
                 if (want_f) {
-                    fnext[sf] = w;
                     next_arcs += rp[w + 1] - rp[w];
+                    if (fbits_next) atomicOr(&fbits_next[w >> 5], 1u << (w & 31));
                 }
-                const int sa = wave_append_slot(want_a, aff_fill);
-                if (want_a) alist[sa] = w;
+                lds_append(want_f, w, s_f, &s_nf);
+                lds_append(want_a, w, s_a, &s_na);
                 bytes += (want_f ? 12 : 0) + (want_a ? 4 : 0);
+                maybe_flush();
             }
         }
     } else {
         const int rc = st->rcount;
         const uint64_t full = rc >= 64 ? ~0ull : ((1ull << rc) - 1ull);
+        // one deleted vertex: any frontier neighbour carries its only bit
+        const bool one = rc == 1;
         const int32_t stride = gridDim.x * blockDim.x;
         for (int32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
             const int32_t w = base + threadIdx.x;
-            bool front = false, first = false;
+            bool heavy = false;
+            uint64_t have = 0ull, acc = 0ull;
+            int32_t b = 0, e = 0;
             if (w < n) {
                 bytes += 1;
                 if (alive[w]) {
-                    const uint64_t have = rmask[w];
+                    have = rmask[w];
                     bytes += 8;
                     if (have != full) {
-                        const int32_t b = rp[w], e = rp[w + 1];
+                        b = rp[w];
+                        e = rp[w + 1];
                         bytes += 8;
-                        uint64_t acc = 0ull;
-                        int32_t p = b;
-                        while (p < e) {
-                            acc |= gain_cur[col[p++]];
-                            if ((acc | have) == full) break;
-                        }
-                        bytes += 12ull * (unsigned long long)(p - b);  // ids and the neighbours' masks read
-                        const uint64_t nw = acc & ~have;
-                        if (nw) {
-                            rmask[w] = have | nw;
-                            gain_next[w] = nw;
-                            front = true;
-                            next_arcs += e - b;
-                            first = mark[w] != epoch;
-                            if (first) mark[w] = epoch;
-                            bytes += 20;
+                        if (e - b > kRbfsLight) {
+                            heavy = true;
+                        } else {
+                            int32_t p = b;
+                            while (p < e) {
+                                int32_t x[4];
+                                bool f[4];
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) x[k] = p + k < e ? col[p + k] : -1;
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) f[k] = x[k] >= 0 && fbit(fbits_cur, x[k]);
+                                if (f[0] | f[1] | f[2] | f[3]) {
+                                    if (one) {
+                                        acc = full;
+                                    } else {
+#pragma unroll
+                                        for (int k = 0; k < 4; ++k)
+                                            if (f[k]) {
+                                                acc |= gain_cur[x[k]];
+                                                bytes += 8;
+                                            }
+                                    }
+                                }
+                                p = min(p + 4, e);
+                                if ((acc | have) == full) break;
+                            }
+                            bytes += 8ull * (unsigned long long)(p - b);  // ids and frontier bit words
                         }
                     }
                 }
             }
-            const int sf = wave_append_slot(front, fnext_count);
-            if (front) fnext[sf] = w;
-            const int sa = wave_append_slot(first, aff_fill);
-            if (first) alist[sa] = w;
+            // the wave scans its heavy vertices together, 64 arcs per step
+            unsigned long long hm = __ballot(heavy);
+            while (hm) {
+                const int src = __ffsll((long long)hm) - 1;
+                hm &= hm - 1ull;
+                const int32_t hb = __shfl(b, src), he = __shfl(e, src);
+                const uint64_t hhave = __shfl(have, src);
+                uint64_t hacc = 0ull;
+                int32_t p0 = hb;
+                for (; p0 < he; p0 += 64) {
+                    const int32_t p = p0 + l;
+                    int32_t x = 0;
+                    bool f = false;
+                    if (p < he) {
+                        x = col[p];
+                        f = fbit(fbits_cur, x);
+                    }
+                    const unsigned long long hits = __ballot(f);
+                    if (!hits) continue;
+                    if (one) {
+                        hacc = full;
+                    } else {
+                        uint64_t gv = f ? gain_cur[x] : 0ull;
+                        if (f) bytes += 8;
+#pragma unroll
+                        for (int o = 32; o >= 1; o >>= 1) gv |= __shfl_xor(gv, o);
+                        hacc |= gv;
+                    }
+                    if ((hacc | hhave) == full) {
+                        p0 += 64;
+                        break;
+                    }
+                }
+                if (l == 0) bytes += 8ull * (unsigned long long)(min(p0, he) - hb);
+                if (l == src) acc = hacc;
+            }
+            bool front = false, first = false;
+            const uint64_t nw = acc & ~have;
+            if (nw) {
+                rmask[w] = have | nw;
+                gain_next[w] = nw;
+                front = true;
+                next_arcs += e - b;
+                first = mark[w] != epoch;
+                if (first) mark[w] = epoch;
+                bytes += 20;
+            }
+            // the wave's 64 vertices are two whole words of the next bitmap
+            if (fbits_next) {
+                const unsigned long long fm = __ballot(front);
+                const int32_t w0 = base + (threadIdx.x & ~63);
+                if (l == 0 && w0 < n) fbits_next[w0 >> 5] = (uint32_t)fm;
+                if (l == 32 && w0 + 32 < n) fbits_next[(w0 >> 5) + 1] = (uint32_t)(fm >> 32);
+            }
+            lds_append(front, w, s_f, &s_nf);
+            lds_append(first, w, s_a, &s_na);
             bytes += (front ? 4 : 0) + (first ? 4 : 0);
+            maybe_flush();
         }
     }
+    __syncthreads();
+    lds_flush(s_f, &s_nf, &s_gb, fnext, fnext_count);
+    lds_flush(s_a, &s_na, &s_gb, alist, aff_fill);
     rbfs_count(bytes, next_arcs, st);
 }
 
 void launch_rbfs_hop(const int32_t* qv, const int32_t* qb, const int* qcount, int32_t n, const int32_t* rp,
-                     const int32_t* col, const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask,
-                     uint64_t* gain_next, int32_t* mark, int32_t* fmark, int32_t* fnext, int* fnext_count,
-                     int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz, hipStream_t s, PullTimer* timer) {
+                     const int32_t* col, const uint8_t* alive, const uint64_t* gain_cur, const uint32_t* fbits_cur,
+                     uint64_t* rmask, uint64_t* gain_next, uint32_t* fbits_next, int32_t* mark, int32_t* fmark,
+                     int32_t* fnext, int* fnext_count, int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz,
+                     hipStream_t s, PullTimer* timer) {
     const bool timed = timer && timer->used < timer->cap;
     if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
-    hipLaunchKernelGGL(k_rbfs_hop, dim3(2048), dim3(256), 0, s, qv, qb, qcount, n, rp, col, alive, gain_cur, rmask,
-                       gain_next, mark, fmark, fnext, fnext_count, alist, aff_fill, st, nnz);
+    hipLaunchKernelGGL(k_rbfs_hop, dim3(512), dim3(256), 0, s, qv, qb, qcount, n, rp, col, alive, gain_cur, fbits_cur,
+                       rmask, gain_next, fbits_next, mark, fmark, fnext, fnext_count, alist, aff_fill, st, nnz);
     if (timed) {
         (void)hipEventRecord(timer->ev[2 * timer->used + 1], s);
         timer->used += 1;
     }
 }
 
-// Zero arr[list[i]] for the previous frontier, then (last block) end hop t:
+// Zero arr[list[i]] and the list's bitmap words for the previous frontier,
+// then (last block) end hop t:
 // record the affected count reached (hopfill[t]), reset the chunk queue, take
 // the next frontier's arcs and clear its list fill.  Every block has read the
 // list's count before it is counted, and the end of the hop touches nothing the
 // blocks write.
 __global__ void k_clear_hop_end(const int32_t* __restrict__ list, const int* count, uint64_t* __restrict__ arr,
-                                RoundState* st, int* hopfill, int t, int h) {
+                                uint32_t* __restrict__ fbits, RoundState* st, int* hopfill, int t, int h) {
     const int cnt = *count;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) arr[list[i]] = 0ull;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+        const int32_t v = list[i];
+        arr[v] = 0ull;
+        fbits[v >> 5] = 0u;
+    }
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) s_last = atomicAdd(&st->blocks_done, 1) == (int)gridDim.x - 1;
@@ -1125,9 +1269,9 @@ __global__ void k_clear_hop_end(const int32_t* __restrict__ list, const int* cou
         }
     }
 }
-void launch_clear_hop_end(const int32_t* list, const int* count, uint64_t* arr, RoundState* st, int* hopfill, int t,
-                          int h, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_hop_end, dim3(512), dim3(256), 0, s, list, count, arr, st, hopfill, t, h);
+void launch_clear_hop_end(const int32_t* list, const int* count, uint64_t* arr, uint32_t* fbits, RoundState* st,
+                          int* hopfill, int t, int h, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_hop_end, dim3(512), dim3(256), 0, s, list, count, arr, fbits, st, hopfill, t, h);
 }
 
 

@@ -944,6 +944,7 @@ struct ExactRun {
     Buf<uint8_t> alive, exact;
     Buf<int32_t> adeg, mark, rlist, alist, qv, qb, srcl, anchor, hopfill, fmark, flA, flB;
     Buf<uint64_t> rmask, gainA, gainB;
+    Buf<uint32_t> fbA, fbB;
     Buf<int64_t> deg, core, ck, cs, cr;
     Buf<RoundState> st;
     Planes PL;
@@ -1009,10 +1010,11 @@ struct ExactRun {
     // committed.
     void delete_round_masked() {
         // R's mask bits and the chunks of hop 1 (the round reset zeroed qcount)
-        launch_enqueue_r(rlist.p, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, 0, rmask.p, gainA.p, nullptr, s,
-                         &st.p->hop_arcs);
+        launch_enqueue_r(rlist.p, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, 0, rmask.p, gainA.p, fbA.p, nullptr,
+                         s, &st.p->hop_arcs);
         int32_t* fl[2] = {flA.p, flB.p};
         uint64_t* gain[2] = {gainA.p, gainB.p};
+        uint32_t* fb[2] = {fbA.p, fbB.p};
         PullTimer* rt = prof_active(g->ctx) ? &g->ctx->timer[2] : nullptr;
         for (int t = 1; t <= h; ++t) {
             const int32_t* src = t == 1 ? rlist.p : fl[(t - 1) & 1];
@@ -1020,14 +1022,15 @@ struct ExactRun {
             if (t > 1) launch_enqueue(src, nullptr, srcn, g->rp, qv.p, qb.p, &st.p->qcount, s, nullptr, st.p, g->nnz);
             // push from the frontier's chunks, or pull into every alive vertex
             // when the frontier holds more than 1/kRbfsPullRatio of the arcs
-            launch_rbfs_hop(qv.p, qb.p, &st.p->qcount, g->n, g->rp, g->col, alive.p, gain[(t - 1) & 1], rmask.p,
-                            gain[t & 1], mark.p, fmark.p, fl[t & 1], &st.p->fcount[t & 1], alist.p, &st.p->aff_fill,
-                            st.p, g->nnz, s, rt);
-            launch_clear_hop_end(src, srcn, gain[(t - 1) & 1], st.p, hopfill.p, t, h, s);
+            launch_rbfs_hop(qv.p, qb.p, &st.p->qcount, g->n, g->rp, g->col, alive.p, gain[(t - 1) & 1],
+                            fb[(t - 1) & 1], rmask.p, gain[t & 1], t < h ? fb[t & 1] : nullptr, mark.p, fmark.p,
+                            fl[t & 1], &st.p->fcount[t & 1], alist.p, &st.p->aff_fill, st.p, g->nnz, s, rt);
+            launch_clear_hop_end(src, srcn, gain[(t - 1) & 1], fb[(t - 1) & 1], st.p, hopfill.p, t, h, s);
         }
         // R leaves X and its chunks are queued (hop_end of hop h zeroed qcount);
         // the alive degrees drop
-        launch_enqueue_r(rlist.p, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, 1, nullptr, nullptr, alive.p, s);
+        launch_enqueue_r(rlist.p, &st.p->rcount, g->rp, qv.p, qb.p, &st.p->qcount, 1, nullptr, nullptr, nullptr,
+                         alive.p, s);
         launch_expand(qv.p, qb.p, &st.p->qcount, g->rp, g->col, alive.p, mark.p, 0, 1, nullptr, nullptr, adeg.p, s);
     }
 
@@ -1060,7 +1063,11 @@ struct ExactRun {
         rmask.alloc(ctx, n);
         gainA.alloc(ctx, n);
         gainB.alloc(ctx, n);
+        fbA.alloc(ctx, ((size_t)n >> 5) + 1);
+        fbB.alloc(ctx, ((size_t)n >> 5) + 1);
         launch_fill_i32(fmark.p, 0, n, s);
+        hip_ok(hipMemsetAsync(fbA.p, 0, fbA.count * sizeof(uint32_t), s));
+        hip_ok(hipMemsetAsync(fbB.p, 0, fbB.count * sizeof(uint32_t), s));
         hip_ok(hipMemsetAsync(rmask.p, 0, 8 * (size_t)n, s));
         hip_ok(hipMemsetAsync(gainA.p, 0, 8 * (size_t)n, s));
         hip_ok(hipMemsetAsync(gainB.p, 0, 8 * (size_t)n, s));

@@ -20,6 +20,9 @@ constexpr int kExpandChunk = 256;
 // A hop of the R-mask BFS pulls (every alive vertex scans its neighbours) once
 // its frontier's arcs exceed 1 / kRbfsPullRatio of all arcs; below that it pushes.
 constexpr int kRbfsPullRatio = 32;
+// In a pulled hop a thread scans a vertex of at most kRbfsLight arcs; the arcs
+// of a larger one are scanned by its whole wave.
+constexpr int kRbfsLight = 32;
 // A BFS hop sweeps every work item once the previous frontier's adjacency
 // exceeds 1 / kSweepRatio of all arcs; below that it pulls only the alive
 // neighbours of the frontier.
@@ -158,15 +161,17 @@ void launch_unstall(RoundState* st, hipStream_t s);
 void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundState* st, int64_t* core,
                           int32_t* rlist, int32_t* mark, hipStream_t s, int32_t* rnd = nullptr);
 // For the listed R (rlist, *rcount): mode 0 sets R's mask bits (bit j for
-// rlist[j]) in rmask and gain, mode 1 removes R from the alive set; both then
-// queue R's adjacency in chunks for the next expansion (*qcount must be 0).
+// rlist[j]) in rmask and gain and R's bits in the frontier bitmap fbits, mode 1
+// removes R from the alive set; both then queue R's adjacency in chunks for the
+// next expansion (*qcount must be 0).
 void launch_enqueue_r(const int32_t* rlist, const int* rcount, const int32_t* rp, int32_t* qv, int32_t* qb, int* qcount,
-                      int mode, uint64_t* rmask, uint64_t* gain, uint8_t* alive, hipStream_t s, long long* arcs = nullptr);
-// arr[list[i]] = 0 for i < *count, then end mask-BFS hop t: hopfill[t] =
-// aff_fill, qcount = 0, hop_arcs = next_arcs (next_arcs = 0), and for t < h a
-// new frontier epoch and fcount[(t+1)&1] = 0.
-void launch_clear_hop_end(const int32_t* list, const int* count, uint64_t* arr, RoundState* st, int* hopfill, int t,
-                          int h, hipStream_t s);
+                      int mode, uint64_t* rmask, uint64_t* gain, uint32_t* fbits, uint8_t* alive, hipStream_t s,
+                      long long* arcs = nullptr);
+// arr[list[i]] = 0 and fbits[list[i] / 32] = 0 for i < *count, then end mask-BFS
+// hop t: hopfill[t] = aff_fill, qcount = 0, hop_arcs = next_arcs (next_arcs =
+// 0), and for t < h a new frontier epoch and fcount[(t+1)&1] = 0.
+void launch_clear_hop_end(const int32_t* list, const int* count, uint64_t* arr, uint32_t* fbits, RoundState* st,
+                          int* hopfill, int t, int h, hipStream_t s);
 // arr_k[list_k[i]] = 0 for three (list, count, array) triples at once; with
 // st != NULL the last block then resets the round state for the next round
 // (unless the sequence is stalled).
@@ -188,12 +193,15 @@ void launch_decide_seg(RoundState* st, int nseg, int* shist, long long* shi, int
 // One hop, in push form (the frontier's chunks queued by launch_enqueue_r /
 // launch_enqueue) or, when the frontier's arcs exceed 1/kRbfsPullRatio of all
 // nnz arcs, in pull form (every alive vertex ORs the frontier masks of its
-// neighbours), decided inside the one kernel.  timer (nullable) brackets it.
+// neighbours), decided inside the one kernel.  The frontier is gain_cur (bits
+// passed on, zero elsewhere) and the bitmap fbits_cur of the same vertices;
+// the next frontier goes to gain_next, fnext and fbits_next (nullable: the last
+// hop's frontier is not needed as a bitmap).  timer (nullable) brackets it.
 void launch_rbfs_hop(const int32_t* qv, const int32_t* qb, const int* qcount, int32_t n, const int32_t* rp,
-                     const int32_t* col, const uint8_t* alive, const uint64_t* gain_cur, uint64_t* rmask,
-                     uint64_t* gain_next, int32_t* mark, int32_t* fmark, int32_t* fnext, int* fnext_count,
-                     int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz, hipStream_t s,
-                     PullTimer* timer = nullptr);
+                     const int32_t* col, const uint8_t* alive, const uint64_t* gain_cur, const uint32_t* fbits_cur,
+                     uint64_t* rmask, uint64_t* gain_next, uint32_t* fbits_next, int32_t* mark, int32_t* fmark,
+                     int32_t* fnext, int* fnext_count, int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz,
+                     hipStream_t s, PullTimer* timer = nullptr);
 // exact decrement for vertices at distance exactly h (deg -= |R within h|), bound otherwise
 void launch_decay_masked(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
                          const int32_t* adeg, const int32_t* anchor, const uint64_t* rmask, int64_t* deg,

@@ -15,6 +15,7 @@
 // >= k[v,i] - 1 are ever read, which is what keeps the work near the paper's
 // O(M deg v) per Compute call even for hubs.
 #include <climits>
+#include <mutex>
 
 #include "kh_common.hpp"
 #include "kh_internal.hpp"
@@ -613,13 +614,22 @@ void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
     const size_t lds = sizeof(uint32_t) << hash_log2;
-    static size_t lds_set = 65536;
-    if (lds > lds_set) {
-        (void)hipFuncSetAttribute((const void*)k_union<kUnionThreads>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)lds);
-        (void)hipFuncSetAttribute((const void*)k_union<kUnionHubThreads>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        lds_set = lds;
+    // The dynamic-LDS limit of both union kernels is raised (never lowered),
+    // per device, under a lock: contexts on several threads launch with
+    // different hash sizes.
+    static std::mutex lds_lock;
+    static size_t lds_set[kMaxDevices] = {};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (lds > 65536 && dev >= 0 && dev < kMaxDevices) {
+        std::lock_guard<std::mutex> g(lds_lock);
+        if (lds > lds_set[dev]) {
+            (void)hipFuncSetAttribute((const void*)k_union<kUnionThreads>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipFuncSetAttribute((const void*)k_union<kUnionHubThreads>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            lds_set[dev] = lds;
+        }
     }
     const bool timed = timer && timer->used < timer->cap;
     if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
