@@ -69,7 +69,7 @@ def measured_traffic(k, stages, hs):
 # the dispatches counted as one launch of a reported kernel (the union's hubs
 # are merged by a second, wider variant inside the same timed launch)
 KERNEL_NAMES = {0: ["k_ms_pull<16>", "k_ms_pull<8>", "k_ms_pull<4>", "k_ms_pull<2>", "k_ms_pull<1>"],
-                1: ["k_union<256>", "k_union<1024>"],
+                1: ["k_union<256>", "k_union<1024>", "k_hub_units", "k_union_merge<256>"],
                 2: ["k_rbfs_hop"]}
 # FETCH_SIZE reads 524,317 KiB for the 1 GiB read by the add kernel of
 # --copy-calib, WRITE_SIZE 1,048,576 KiB for its 1 GiB write
@@ -362,12 +362,12 @@ def bench_cl4m(kh, ctx, args):
     for eps in ([] if args.dev_only else [float(x) for x in args.cl4m_eps.split(",")]):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        _, res = kh.core(G, 3, epsilon=eps, delta=0.05, seed=1, out=core_out, dense=True, prune=True,
-                         lazy_init=3 in args.lazy_set)
+        _, res = kh.core(G, 3, epsilon=eps, delta=0.05, seed=1, out=core_out, dense=not args.cl4m_no_dense,
+                         prune=True, lazy_init=3 in args.lazy_set)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         log(f"cl4m sampled h=3 eps={eps}: {dt:.1f}s")
-        out[f"eps{eps}"] = {"seconds": round(dt, 3), **{k: res[k] for k in (
+        out[f"eps{eps}"] = {"seconds": round(dt, 3), "with_alg7": not args.cl4m_no_dense, **{k: res[k] for k in (
             "M_used", "M_dense_used", "rounds", "max_core", "dense_k", "dense_size", "dense_density",
             "list_elements")}}
     del G
@@ -483,6 +483,7 @@ def main():
                     help="seconds after the last arrival before queued requests are withdrawn")
     ap.add_argument("--cl4m", action="store_true", help="also measure the 4M-vertex sampled workload")
     ap.add_argument("--cl4m-eps", default="0.5,0.25")
+    ap.add_argument("--cl4m-no-dense", action="store_true", help="--cl4m: Core only, without Alg. 7")
     ap.add_argument("--dev-n", type=int, default=100_000)
     ap.add_argument("--dev-only", action="store_true", help="--cl4m: only the deviation study")
     ap.add_argument("--sbm", action="store_true", help="also measure the block-model scaling series")

@@ -492,6 +492,9 @@ __global__ void k_level_reset(RoundState* st, int level) {
     st->wl_count = 0;
     st->rc_count = 0;
     st->hub_count = 0;
+    st->unit_count = 0;
+    st->slot_count = 0;
+    st->giant_count = 0;
     st->changed_count[level & 1] = 0;
 }
 void launch_level_reset(RoundState* st, int level, hipStream_t s) {

@@ -1326,6 +1326,37 @@ struct SampledRun {
     Lists L;
     Candidates cands;
     RoundState fin{};
+    // hubs split into slices merged in parallel (HubSplit); slice size from
+    // KH_HUB_SLICE (arcs; 0 turns splitting off)
+    HubSplit split;
+    Buf<int4> units, giants;
+    Buf<uint32_t> pkeys;
+    Buf<int32_t> pmeta, phk;
+
+    void alloc_split() {
+        kh_context* ctx = g->ctx;
+        int64_t sl = kHubSlice;
+        if (const char* e = std::getenv("KH_HUB_SLICE")) sl = std::atoll(e);
+        if (sl <= 0 || h < 2 || g->nnz <= 2 * (int64_t)sl) return;
+        sl = std::min<int64_t>(sl, INT32_MAX);
+        // a split hub has more than sl arcs and at most deg / sl + 1 slices
+        const int64_t slots = 2 * (g->nnz / sl) + 1;
+        const int64_t ucap = g->nnz / (kHubDegree + 1) + 1 + slots;
+        units.alloc(ctx, (size_t)ucap);
+        giants.alloc(ctx, (size_t)(g->nnz / sl + 1));
+        pkeys.alloc(ctx, (size_t)slots * (size_t)M);
+        pmeta.alloc(ctx, (size_t)slots * 4);
+        phk.alloc(ctx, (size_t)slots * 256);
+        split.slice = (int32_t)sl;
+        split.unit = units.p;
+        split.unit_cap = (int32_t)ucap;
+        split.giant = giants.p;
+        split.pkeys = pkeys.p;
+        split.pcap = M;
+        split.pmeta = pmeta.p;
+        split.phk = phk.p;
+        split.slot_cap = (int32_t)slots;
+    }
 
     void alloc_common() {
         kh_context* ctx = g->ctx;
@@ -1352,6 +1383,7 @@ struct SampledRun {
         cr.alloc(ctx, (size_t)n + 1);
         partials.alloc(ctx, (size_t)n / 2048 + 2);
         st.alloc(ctx, 1);
+        alloc_split();
     }
 
     void build_lists() {
@@ -1485,7 +1517,8 @@ struct SampledRun {
                     else
                         launch_union(rc.p, &st.p->rc_count, n, g->rp, g->col, alive.p, rank.p, M, Mv, L.hash_log2,
                                      L.view(i - 1), L.view(i), cursor.p, order.p, changed[i & 1],
-                                     &st.p->changed_count[i & 1], st.p, q, utimer, hubs.p, &st.p->hub_count);
+                                     &st.p->changed_count[i & 1], st.p, q, utimer, hubs.p, &st.p->hub_count,
+                                     &split);
                 }
                 launch_estimate(changed[h & 1], &st.p->changed_count[h & 1], n, alive.p, rank.p, L.size[h].p,
                                 L.kk[h].p, M, Mv, d.p, st.p, q);

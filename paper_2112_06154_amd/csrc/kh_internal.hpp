@@ -38,6 +38,8 @@ constexpr int kUnionThreads = 256;
 constexpr int kUnionHubThreads = 1024;
 // Vertices with more neighbours than this order their arcs by list head rank in the union.
 constexpr int kHubDegree = 1024;
+// Arcs per slice of a hub merged in parallel (more arcs: split; see HubSplit).
+constexpr int kHubSlice = 8192;
 
 // Per-run device state for the bulk peeling rounds (one instance in device memory).
 struct RoundState {
@@ -79,6 +81,10 @@ struct RoundState {
     long long hop_arcs;              // arcs of the current R-mask BFS frontier (push/pull choice)
     long long next_arcs;             // arcs of the frontier the current hop builds
     long long hop_log[4];            // trace: frontier arcs of mask-BFS hops 1..3 of the last round
+    int unit_count;                  // sampled peel: work items of the hub launch (whole hubs and slices)
+    int slot_count;                  // sampled peel: partial-list slots taken by hub slices
+    int giant_count;                 // sampled peel: hubs split into slices
+    int pad_units;
 };
 
 // Optional HIP-event timing of every launch of a kernel, on the stream it is
@@ -300,12 +306,30 @@ void launch_cap_next(const int32_t* rp, const int32_t* col, int32_t n, int32_t M
 void launch_union1(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
                    const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, LevelView cur,
                    int32_t* changed, int* changed_count, RoundState* st, hipStream_t s);
-// Level i >= 2.
+// Hubs of a level's worklist with more than `slice` arcs are split: their
+// slices of at most `slice` arcs are merged in parallel like vertices of their
+// own, each into a partial list (its entries of rank >= its own level), and the
+// hub then merges its slices' partial lists.  Unions are associative under the
+// truncation (the level of a union is at least every part's level, and above
+// that level every part's list is complete), so the result is the hub's list.
+struct HubSplit {
+    int32_t slice = 0;          // arcs per slice (0: no split)
+    int4* unit = nullptr;       // hub-launch work items: (vertex, first arc, end arc, slot or -1)
+    int32_t unit_cap = 0;
+    int4* giant = nullptr;      // split hubs: (vertex, first slot, slices, 0)
+    uint32_t* pkeys = nullptr;  // partial lists: slot q at pkeys + q * pcap, grouped by rank
+    int32_t pcap = 0;           // >= M
+    int32_t* pmeta = nullptr;   // per slot: size, level, largest neighbour level, head rank
+    int32_t* phk = nullptr;     // per slot: the slice's alive neighbours by level (256 counts)
+    int32_t slot_cap = 0;
+};
+// Level i >= 2.  hubs (nullable): vertices of the worklist with more than
+// kHubDegree arcs, merged by wider blocks (split per `split` when it is on).
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, int hash_log2,
                   LevelView prev, LevelView cur, int32_t* cursor, int32_t* order, int32_t* changed,
                   int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer = nullptr,
-                  const int32_t* hubs = nullptr, const int* hub_count = nullptr);
+                  const int32_t* hubs = nullptr, const int* hub_count = nullptr, const HubSplit* split = nullptr);
 // Propagate the deletions and changes of level i-1 over the arcs of the queued
 // vertices: mark + append alive neighbours, fold the highest lost rank into
 // lostmax[], and keep m[.,i] current.

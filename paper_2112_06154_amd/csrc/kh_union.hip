@@ -394,7 +394,7 @@ __global__ __launch_bounds__(BS) void k_union(const int32_t* __restrict__ workli
                                                int32_t M0, const int32_t* __restrict__ Mv, int hash_log2,
                                                LevelView prev, LevelView cur, int32_t* __restrict__ cursor,
                                                int32_t* __restrict__ order, int32_t* __restrict__ changed,
-                                               int* changed_count, RoundState* st) {
+                                               int* changed_count, RoundState* st, HubSplit sp) {
     extern __shared__ uint32_t tab[];
     __shared__ int hist[256];
     __shared__ int hk[256];
@@ -407,14 +407,28 @@ __global__ __launch_bounds__(BS) void k_union(const int32_t* __restrict__ workli
     const int bs = blockDim.x;
     const int hcap = 1 << hash_log2;
     HashSet H{tab, (uint32_t)(hcap - 1), 32 - hash_log2, &s_count, hist, M0};
-    const int total = worklist ? *wl_count : n;
+    // work items: vertices (worklist, or all), or with sp.unit the hub launch's
+    // units -- a whole hub, or one slice of a split hub whose result goes to a
+    // partial-list slot instead of B[v,i]
+    const int total = sp.unit ? *wl_count : (worklist ? *wl_count : n);
     unsigned long long elems = 0, bytes = 0;
     for (int wi = blockIdx.x; wi < total; wi += gridDim.x) {
-        const int32_t v = worklist ? worklist[wi] : wi;
+        int32_t v, b, e;
+        int slot = -1;
+        if (sp.unit) {
+            const int4 u = sp.unit[wi];
+            v = u.x;
+            b = u.y;
+            e = u.z;
+            slot = u.w;
+        } else {
+            v = worklist ? worklist[wi] : wi;
+            b = rp[v];
+            e = rp[v + 1];
+        }
         if (!alive[v]) continue;
         const int M = Mv ? Mv[v] : M0;
         H.M = M;
-        const int32_t b = rp[v], e = rp[v + 1];
         const int32_t deg = e - b;
         if (tid == 0) bytes += 8 + 6;  // rp[v], rank/alive/old state of v
         // small vertices: thread tid owns arc b + tid for the whole computation;
@@ -560,6 +574,28 @@ __global__ __launch_bounds__(BS) void k_union(const int32_t* __restrict__ workli
             s_head = hr;
         }
         __syncthreads();
+        if (slot >= 0) {
+            // a slice: its partial list (entries of rank >= its level, grouped by
+            // rank), its level, largest neighbour level, head and level histogram
+            uint32_t* pout = sp.pkeys + (size_t)slot * sp.pcap;
+            for (int t = tid; t < hcap; t += bs) {
+                const uint32_t key = tab[t];
+                if (key != kEmptyKey) {
+                    const int rk = key_rank(key);
+                    if (rk >= k) pout[atomicAdd(&hist[rk], 1)] = key;
+                }
+            }
+            for (int t = tid; t < 256; t += bs) sp.phk[(size_t)slot * 256 + t] = hk[t];
+            if (tid == 0) {
+                bytes += 4ull * (unsigned long long)s_size + 1040;
+                sp.pmeta[4 * slot + 0] = s_size;
+                sp.pmeta[4 * slot + 1] = s_k;
+                sp.pmeta[4 * slot + 2] = kmax;
+                sp.pmeta[4 * slot + 3] = s_size > 0 ? s_head : -1;
+            }
+            __syncthreads();
+            continue;
+        }
         const bool chg = changed && (s_ok != s_k || s_os != s_size);
         uint32_t* out = keys_at(cur, v);
         if (chg) {
@@ -606,11 +642,210 @@ __global__ __launch_bounds__(BS) void k_union(const int32_t* __restrict__ workli
     }
 }
 
+// Work items of the hub launch: every hub of the list whole, or (more than
+// sp.slice arcs) as slices of at least sp.slice arcs, at most kMergeThreads of
+// them, each with a partial-list slot; a split hub is also listed for the merge.
+constexpr int kMergeThreads = 256;
+
+__global__ void k_hub_units(const int32_t* __restrict__ hubs, const int* hub_count, const int32_t* __restrict__ rp,
+                            HubSplit sp, RoundState* st) {
+    const int total = *hub_count;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x; base < total; base += stride) {
+        const int i = base + threadIdx.x;
+        int32_t v = 0, b = 0, e = 0, sl = 1;
+        int ns = 0;
+        if (i < total) {
+            v = hubs[i];
+            b = rp[v];
+            e = rp[v + 1];
+            const int32_t deg = e - b;
+            sl = max(sp.slice, (deg + kMergeThreads - 1) / kMergeThreads);
+            ns = (deg + sl - 1) / sl;
+        }
+        // slots (split hubs), then work items, one atomic per wave each
+        const int nslot = ns > 1 ? ns : 0;
+        const int si = wave_incl_scan(nslot);
+        int sb = 0;
+        if (lane_id() == 63 && si > 0) sb = atomicAdd(&st->slot_count, si);
+        sb = __shfl(sb, 63);
+        int q0 = sb + si - nslot;
+        // the slots are sized for every split the hubs of a graph can need; a
+        // hub that found none left is merged whole
+        const bool split = nslot > 0 && q0 + nslot <= sp.slot_cap;
+        const int nunit = i < total ? (split ? ns : 1) : 0;
+        const int ui = wave_incl_scan(nunit);
+        int ub = 0;
+        if (lane_id() == 63 && ui > 0) ub = atomicAdd(&st->unit_count, ui);
+        ub = __shfl(ub, 63);
+        const int u0 = ub + ui - nunit;
+        if (i < total) {
+            if (split) {
+                for (int j = 0; j < ns; ++j) sp.unit[u0 + j] = make_int4(v, b + j * sl, min(e, b + (j + 1) * sl), q0 + j);
+            } else {
+                sp.unit[u0] = make_int4(v, b, e, -1);
+            }
+        }
+        const int gs = wave_append_slot(split, &st->giant_count);
+        if (split) sp.giant[gs] = make_int4(v, q0, ns, 0);
+    }
+}
+
+// The merge of a split hub: its slices' partial lists stand for the neighbours'
+// lists.  Above F, the largest level of a slice, every partial list holds all of
+// its slice's entries, and the hub's level is at least F (each slice's entries
+// are a subset of the hub's, and the neighbour levels bound both), so the walk
+// from the top stops at F.  m counts the neighbours at the final level from the
+// slices' histograms; the cut flag compares with the largest neighbour level.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_union_merge(const int* giant_count, const uint8_t* __restrict__ alive,
+                                                     const uint8_t* __restrict__ rank, int32_t M0,
+                                                     const int32_t* __restrict__ Mv, int hash_log2, LevelView cur,
+                                                     int32_t* __restrict__ changed, int* changed_count,
+                                                     RoundState* st, HubSplit sp) {
+    extern __shared__ uint32_t tab[];
+    __shared__ int hist[256];
+    __shared__ int s_offs[BS], s_scan[BS / 64];
+    __shared__ long long s_seg[BS];
+    __shared__ int s_kmax, s_floor, s_htop, s_count, s_k, s_size, s_ok, s_os, s_lost, s_head, s_m;
+    const int tid = threadIdx.x;
+    const int bs = blockDim.x;
+    const int hcap = 1 << hash_log2;
+    HashSet H{tab, (uint32_t)(hcap - 1), 32 - hash_log2, &s_count, hist, M0};
+    LevelView pv{};
+    pv.keys = sp.pkeys;
+    const int total = *giant_count;
+    unsigned long long elems = 0, bytes = 0;
+    for (int gi = blockIdx.x; gi < total; gi += gridDim.x) {
+        const int4 G = sp.giant[gi];
+        const int32_t v = G.x;
+        if (!alive[v]) continue;
+        const int M = Mv ? Mv[v] : M0;
+        H.M = M;
+        const int ns = G.z;
+        for (int t = tid; t < hcap; t += bs) tab[t] = kEmptyKey;
+        if (tid < 256) hist[tid] = 0;
+        if (tid == 0) {
+            s_kmax = 0;
+            s_floor = 0;
+            s_htop = rank[v];
+            s_count = 0;
+            s_m = 0;
+            s_ok = cur.k[v];
+            s_os = cur.size[v];
+            s_lost = -1;
+            bytes += 16 + 6;  // work item, rank/alive/old state of v
+        }
+        __syncthreads();
+        ArcState mine{0, 0, 0};
+        int kmax_l = 0, floor_l = 0, htop_l = -1;
+        if (tid < ns) {
+            const int q = G.y + tid;
+            mine.size = sp.pmeta[4 * q + 0];
+            mine.off = (int64_t)q * sp.pcap;
+            floor_l = sp.pmeta[4 * q + 1];
+            kmax_l = sp.pmeta[4 * q + 2];
+            if (mine.size > 0) htop_l = sp.pmeta[4 * q + 3];
+            bytes += 16;
+        }
+        kmax_l = wave_max_i(kmax_l);
+        floor_l = wave_max_i(floor_l);
+        htop_l = wave_max_i(htop_l);
+        if (lane_id() == 0) {
+            atomicMax(&s_kmax, kmax_l);
+            atomicMax(&s_floor, floor_l);
+            atomicMax(&s_htop, htop_l);
+        }
+        __syncthreads();
+        const int kmax = s_kmax;
+        const int F = s_floor;
+        const int htop = s_htop;
+        const int rv = rank[v];
+        int k = F;
+        const int lo0 = (changed && s_ok >= F && s_ok <= htop) ? s_ok : htop + 1;
+        if (lo0 <= htop) {
+            if (tid == 0 && rv >= lo0) hs_insert(H, sample_key(rv, v));
+            const int start = mine.cur;
+            const int len = arc_run(sp.pkeys + mine.off, mine, lo0, bytes);
+            insert_runs<BS>(len, mine.off + start, pv, H, M, s_offs, s_seg, s_scan, elems, bytes);
+        }
+        for (int L = min(lo0 - 1, htop); L >= F; --L) {
+            if (tid == 0 && rv == L && *(volatile int*)&s_count <= M) hs_insert(H, sample_key(L, v));
+            const int start = mine.cur;
+            const int len = arc_run(sp.pkeys + mine.off, mine, L, bytes);
+            insert_runs<BS>(len, mine.off + start, pv, H, M, s_offs, s_seg, s_scan, elems, bytes);
+            const int over = s_count > M;
+            __syncthreads();
+            if (over) {
+                k = L + 1;
+                break;
+            }
+        }
+        if (tid == 0) {
+            int run = 0, hr = 0;
+            for (int L = 255; L >= k; --L) {
+                const int c = hist[L];
+                if (c > 0 && run == 0) hr = L;
+                hist[L] = run;
+                run += c;
+            }
+            s_k = k;
+            s_size = run;
+            s_head = hr;
+        }
+        __syncthreads();
+        // m: alive neighbours at the final level, summed over the slices
+        int mc = tid < ns ? sp.phk[(size_t)(G.y + tid) * 256 + s_k] : 0;
+        mc = wave_sum_i(mc);
+        if (lane_id() == 0 && mc) atomicAdd(&s_m, mc);
+        const bool chg = changed && (s_ok != s_k || s_os != s_size);
+        uint32_t* out = keys_at(cur, v);
+        if (chg) {
+            int lm = -1;
+            for (int t = tid; t < s_os; t += bs) {
+                const uint32_t key = out[t];
+                if (!hs_contains(H, key)) lm = max(lm, key_rank(key));
+            }
+            if (tid == 0) bytes += 4ull * (unsigned long long)s_os;
+            lm = wave_max_i(lm);
+            if (lane_id() == 0 && lm >= 0) atomicMax(&s_lost, lm);
+        }
+        __syncthreads();
+        for (int t = tid; t < hcap; t += bs) {
+            const uint32_t key = tab[t];
+            if (key != kEmptyKey) {
+                const int rk = key_rank(key);
+                if (rk >= k) out[atomicAdd(&hist[rk], 1)] = key;
+            }
+        }
+        if (tid == 0) {
+            bytes += 4ull * (unsigned long long)s_size + 4ull * ns + 17;
+            cur.size[v] = s_size;
+            cur.k[v] = (uint8_t)s_k;
+            cur.meta[v] = pack_meta(s_size, s_k, s_head);
+            cur.m[v] = s_m;
+            cur.cut[v] = s_k > kmax ? 1 : 0;
+            if (chg) {
+                cur.lost[v] = (int16_t)s_lost;
+                cur.kold[v] = (uint8_t)s_ok;
+                changed[atomicAdd(changed_count, 1)] = v;
+            }
+        }
+        __syncthreads();
+    }
+    elems = (unsigned long long)wave_sum_ll((long long)elems);
+    bytes = (unsigned long long)wave_sum_ll((long long)bytes);
+    if (lane_id() == 0) {
+        if (elems) atomicAdd(&st->elems, elems);
+        if (bytes) atomicAdd(&st->union_bytes, bytes);
+    }
+}
+
 void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const int32_t* rp, const int32_t* col,
                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, int hash_log2,
                   LevelView prev, LevelView cur, int32_t* cursor, int32_t* order, int32_t* changed,
                   int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer, const int32_t* hubs,
-                  const int* hub_count) {
+                  const int* hub_count, const HubSplit* split) {
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
     const size_t lds = sizeof(uint32_t) << hash_log2;
@@ -628,18 +863,30 @@ void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             (void)hipFuncSetAttribute((const void*)k_union<kUnionHubThreads>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipFuncSetAttribute((const void*)k_union_merge<kMergeThreads>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             lds_set[dev] = lds;
         }
     }
     const bool timed = timer && timer->used < timer->cap;
     if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
+    const HubSplit none{};
     hipLaunchKernelGGL(k_union<kUnionThreads>, dim3(grid), dim3(kUnionThreads), lds, s, worklist, wl_count, n, rp, col,
-                       alive, rank, M, Mv, hash_log2, prev, cur, cursor, order, changed, changed_count, st);
-    // hubs of the worklist: wider blocks for their neighbour walks
-    if (hubs)
+                       alive, rank, M, Mv, hash_log2, prev, cur, cursor, order, changed, changed_count, st, none);
+    // hubs of the worklist: wider blocks for their neighbour walks; split into
+    // slices merged in parallel, then merged per hub, when splitting is on
+    if (hubs && split && split->slice > 0) {
+        hipLaunchKernelGGL(k_hub_units, dim3(8), dim3(256), 0, s, hubs, hub_count, rp, *split, st);
+        hipLaunchKernelGGL(k_union<kUnionHubThreads>, dim3(512), dim3(kUnionHubThreads), lds, s, hubs,
+                           &st->unit_count, n, rp, col, alive, rank, M, Mv, hash_log2, prev, cur, cursor, order,
+                           changed, changed_count, st, *split);
+        hipLaunchKernelGGL(k_union_merge<kMergeThreads>, dim3(256), dim3(kMergeThreads), lds, s, &st->giant_count,
+                           alive, rank, M, Mv, hash_log2, cur, changed, changed_count, st, *split);
+    } else if (hubs) {
         hipLaunchKernelGGL(k_union<kUnionHubThreads>, dim3(512), dim3(kUnionHubThreads), lds, s, hubs, hub_count, n,
                            rp, col, alive, rank, M, Mv, hash_log2, prev, cur, cursor, order, changed, changed_count,
-                           st);
+                           st, none);
+    }
     if (timed) {
         (void)hipEventRecord(timer->ev[2 * timer->used + 1], s);
         timer->used += 1;
