@@ -76,7 +76,7 @@ KERNEL_NAMES = {0: ["k_ms_pull<16>", "k_ms_pull<8>", "k_ms_pull<4>", "k_ms_pull<
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
-def pmc_summarize(fetch_dir, write_dir, stages, hs):
+def pmc_summarize(fetch_dir, write_dir, stages, hs, out_path=None):
     """Per-launch HBM bytes of the two reported kernels from rocprofv3
     counter_collection.csv files of a FETCH_SIZE run and a WRITE_SIZE run of
     the same command (KiB per dispatch, scaled by the copy calibration), plus
@@ -99,7 +99,8 @@ def pmc_summarize(fetch_dir, write_dir, stages, hs):
 
     fe, wr = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
     out = {"scale": {"FETCH_SIZE": FETCH_SCALE, "WRITE_SIZE": WRITE_SCALE},
-           "calibration": {k: {"fetch_kib": v[1] / v[0]} for k, v in fe.items() if "at::native" in k}}
+           "calibration": {k: {"fetch_kib": v[1] / v[0], "write_kib": wr[k][1] / wr[k][0] if k in wr else None}
+                           for k, v in fe.items() if "at::native" in k}}
     for k, names in KERNEL_NAMES.items():
         first = names[0]
         if first not in fe or first not in wr:
@@ -112,9 +113,44 @@ def pmc_summarize(fetch_dir, write_dir, stages, hs):
         out[str(k)] = {"kernels": names, "source_sha256_16": source_hash(k), "stage": stages, "h": hs,
                        "launches": launches, "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib,
                        "bytes_per_launch": int(1024 * (FETCH_SCALE * f_kib + WRITE_SCALE * w_kib))}
-    with open(TRAFFIC_FILE, "w") as fh:
+    with open(out_path or TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
+
+
+def trace_hops(path):
+    """Mask-BFS hop durations of the exact peel from a rocprofv3 kernel_trace.csv
+    (--kernel-trace with k_rbfs_hop and k_select_commit included): dispatches
+    are numbered by their hop within the round (count since the round's
+    k_select_commit) and summed per hop and per duration bucket."""
+    import collections
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            nm = r["Kernel_Name"]
+            kind = "hop" if "k_rbfs_hop" in nm else ("sel" if "k_select_commit" in nm else None)
+            if kind:
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), kind))
+    rows.sort()
+    by_hop = collections.defaultdict(lambda: [0, 0])
+    edges = [5e3, 1e4, 2e4, 5e4, 1e5, 2e5, 5e5, 1e6, float("inf")]
+    buckets = collections.defaultdict(lambda: [0, 0])
+    hop = 0
+    for s0, e0, kind in rows:
+        if kind == "sel":
+            hop = 0
+            continue
+        hop += 1
+        d = e0 - s0
+        by_hop[hop][0] += 1
+        by_hop[hop][1] += d
+        b = next(x for x in edges if d < x)
+        buckets[b][0] += 1
+        buckets[b][1] += d
+    out = {"hops": {h: {"dispatches": c, "seconds": t / 1e9, "avg_us": t / c / 1e3} for h, (c, t) in by_hop.items()},
+           "buckets_us": {("<%g" % (b / 1e3)): {"dispatches": c, "seconds": t / 1e9} for b, (c, t) in buckets.items()}}
+    print(json.dumps(out, indent=1))
 
 
 def log(*a):
@@ -459,7 +495,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--budget-s", type=float, default=450.0,
                     help="wall-clock budget of the whole run; warmup and timed steps are cut to fit")
-    ap.add_argument("--step-estimate-s", type=float, default=240.0,
+    ap.add_argument("--step-estimate-s", type=float, default=120.0,
                     help="assumed step time before one has been measured (decides whether a warmup step fits)")
     ap.add_argument("--stages", default="exact,sampled", help="comma list of hdeg,exact,sampled")
     ap.add_argument("--hs", default="2,3")
@@ -491,9 +527,17 @@ def main():
     ap.add_argument("--sbm-reps", type=int, default=3)
     ap.add_argument("--skip-main", action="store_true",
                     help="only the --batch / --serve / --cl4m / --sbm measurements")
+    ap.add_argument("--trace-hops", default=None, metavar="KERNEL_TRACE_CSV",
+                    help="summarise the exact peel's mask-BFS hops from a rocprofv3 kernel trace and exit")
+    ap.add_argument("--pmc-out", default=None, help="--pmc-summarize: write here instead of profiles/")
+    ap.add_argument("--no-prewarm", action="store_true",
+                    help="skip the small-graph warm-up (counter runs: only the timed step's dispatches)")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_counters.json from two rocprofv3 --pmc runs of this command")
     args = ap.parse_args()
+    if args.trace_hops:
+        trace_hops(args.trace_hops)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the build has no multi-GPU path, "
                                    "so --gpus must be 1"}))
@@ -504,7 +548,7 @@ def main():
     lazy_hs = {int(x) for x in args.lazy_hs.split(",") if x}
     args.lazy_set = lazy_hs
     if args.pmc_summarize:
-        pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], stages, hs)
+        pmc_summarize(args.pmc_summarize[0], args.pmc_summarize[1], stages, hs, args.pmc_out)
         return
 
     import concurrent.futures
@@ -541,7 +585,7 @@ def main():
     small = gg.chung_lu(20_000, 200_000, 2.1, seed=3)
     Gs = kh.Graph.from_gg(ctx, small)
     outs = torch.empty(small.n, dtype=torch.int32, device="cuda:0")
-    for h in hs:
+    for h in ([] if args.no_prewarm else hs):
         kh.core(Gs, h, out=outs, dense=True, prune=True)
         kh.core(Gs, h, epsilon=0.5, delta=0.05, seed=1, out=outs, dense=True, prune=True, lazy_init=h in lazy_hs)
     torch.cuda.synchronize()

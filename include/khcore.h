@@ -153,7 +153,12 @@ int64_t kh_graph_nnz(const kh_graph *g);
  * KH_ENOTIMPL (sampled path with n >= 2^24, or an integer M whose LDS hash set,
  * 2 (M + 1025) entries rounded up to a power of two, does not fit one
  * work-group's LDS next to ~17 KiB of other state: M <= 15,359 with 160 KiB),
- * KH_EOVERFLOW (core number above INT32_MAX), KH_ENOMEM, KH_EDEVICE. */
+ * KH_EOVERFLOW (core number above INT32_MAX), KH_ENOMEM, KH_EDEVICE.
+ * Environment (none changes a result): read per call, KH_HUB_SLICE = arcs per
+ * slice of a hub merged in parallel by the sampled peel (default 8192, 0 = off)
+ * and KH_NO_GRAPH = 1 (launch round loops directly instead of replaying
+ * captured HIP graphs); read once per process, KH_TRACE = 1 (round progress on
+ * stderr) and KH_HEARTBEAT = seconds between progress lines of long peels. */
 kh_status kh_core(kh_graph *g, const kh_params *params, int32_t *core_out, kh_result *res, void *stream);
 
 /* kh_core over `count` graphs at once (same params for all), for many small
@@ -170,9 +175,9 @@ kh_status kh_core(kh_graph *g, const kh_params *params, int32_t *core_out, kh_re
  *     KH_WANT_DENSE, the dense_* fields of that graph; rounds, edges_traversed,
  *     arcs_scanned, list_elements and seconds describe the packed union the
  *     graph was part of (equal across its graphs).
- * Graphs are packed by size: a union holds graphs within a factor 4 of its
- * smallest one, and at most 2^24 - 1 vertices (sampled) or 2^31 - 2 vertices and
- * 2^31 - 1 arcs (exact); a batch runs as consecutive unions.
+ * Graphs are packed in order of size into unions of at most 2^24 - 1 vertices
+ * (sampled) or 2^31 - 2 vertices and 2^31 - 1 arcs (exact); a batch runs as
+ * consecutive unions.
  * Errors: as kh_core; KH_ENOTIMPL with KH_EARLY_STOP (its stopping test is per
  * graph).  On error no result of the batch is valid. */
 kh_status kh_core_batch(kh_context *ctx, int32_t count, kh_graph *const *graphs, const kh_params *params,

@@ -359,7 +359,7 @@ __global__ void k_enqueue(const int32_t* __restrict__ list, const int* lo_p, con
                           const int32_t* __restrict__ rp, int32_t* __restrict__ qv, int32_t* __restrict__ qb,
                           int* qcount, long long* arcs, const RoundState* pull_st, int64_t nnz) {
     // a mask-BFS hop that pulls needs no chunk queue
-    if (pull_st && nnz > 0 && pull_st->hop_arcs * (long long)kRbfsPullRatio > nnz) return;
+    if (pull_st && nnz > 0 && pull_st->hop_arcs * (long long)pull_st->pull_ratio > nnz) return;
     const int lo = lo_p ? *lo_p : 0;
     const int hi = *hi_p;
     const int stride = gridDim.x * blockDim.x;
@@ -388,8 +388,9 @@ __global__ void k_enqueue(const int32_t* __restrict__ list, const int* lo_p, con
     }
 }
 void launch_enqueue(const int32_t* list, const int* lo, const int* hi, const int32_t* rp, int32_t* qv, int32_t* qb,
-                    int* qcount, hipStream_t s, long long* arcs, const RoundState* pull_st, int64_t nnz) {
-    hipLaunchKernelGGL(k_enqueue, dim3(512), dim3(256), 0, s, list, lo, hi, rp, qv, qb, qcount, arcs, pull_st, nnz);
+                    int* qcount, hipStream_t s, long long* arcs, const RoundState* pull_st, int64_t nnz, int grid) {
+    hipLaunchKernelGGL(k_enqueue, dim3(grid > 0 ? grid : 128), dim3(256), 0, s, list, lo, hi, rp, qv, qb, qcount, arcs,
+                       pull_st, nnz);
 }
 
 __global__ void k_enqueue_r(const int32_t* __restrict__ rlist, const int* rcount, const int32_t* __restrict__ rp,
@@ -495,6 +496,7 @@ __global__ void k_level_reset(RoundState* st, int level) {
     st->unit_count = 0;
     st->slot_count = 0;
     st->giant_count = 0;
+    st->small_count = 0;
     st->changed_count[level & 1] = 0;
 }
 void launch_level_reset(RoundState* st, int level, hipStream_t s) {
@@ -956,7 +958,7 @@ void launch_select_commit(const int64_t* key, uint8_t* alive, int32_t n, RoundSt
 // gives |R ∩ N(v;h,X)| as a popcount when |R| <= 64 (R's bits are set by
 // launch_enqueue_r).
 __device__ __forceinline__ bool rbfs_pulls(const RoundState* st, int64_t nnz) {
-    return nnz > 0 && st->hop_arcs * (long long)kRbfsPullRatio > nnz;
+    return nnz > 0 && st->hop_arcs * (long long)st->pull_ratio > nnz;
 }
 
 // Algorithmic bytes of a block of the mask BFS and the arcs of the vertices it
@@ -1230,11 +1232,12 @@ void launch_rbfs_hop(const int32_t* qv, const int32_t* qb, const int* qcount, in
                      const int32_t* col, const uint8_t* alive, const uint64_t* gain_cur, const uint32_t* fbits_cur,
                      uint64_t* rmask, uint64_t* gain_next, uint32_t* fbits_next, int32_t* mark, int32_t* fmark,
                      int32_t* fnext, int* fnext_count, int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz,
-                     hipStream_t s, PullTimer* timer) {
+                     hipStream_t s, PullTimer* timer, int grid) {
     const bool timed = timer && timer->used < timer->cap;
     if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
-    hipLaunchKernelGGL(k_rbfs_hop, dim3(512), dim3(256), 0, s, qv, qb, qcount, n, rp, col, alive, gain_cur, fbits_cur,
-                       rmask, gain_next, fbits_next, mark, fmark, fnext, fnext_count, alist, aff_fill, st, nnz);
+    hipLaunchKernelGGL(k_rbfs_hop, dim3(grid > 0 ? grid : 512), dim3(256), 0, s, qv, qb, qcount, n, rp, col, alive,
+                       gain_cur, fbits_cur, rmask, gain_next, fbits_next, mark, fmark, fnext, fnext_count, alist,
+                       aff_fill, st, nnz);
     if (timed) {
         (void)hipEventRecord(timer->ev[2 * timer->used + 1], s);
         timer->used += 1;
@@ -1273,8 +1276,9 @@ __global__ void k_clear_hop_end(const int32_t* __restrict__ list, const int* cou
     }
 }
 void launch_clear_hop_end(const int32_t* list, const int* count, uint64_t* arr, uint32_t* fbits, RoundState* st,
-                          int* hopfill, int t, int h, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_hop_end, dim3(512), dim3(256), 0, s, list, count, arr, fbits, st, hopfill, t, h);
+                          int* hopfill, int t, int h, hipStream_t s, int grid) {
+    hipLaunchKernelGGL(k_clear_hop_end, dim3(grid > 0 ? grid : 128), dim3(256), 0, s, list, count, arr, fbits, st,
+                       hopfill, t, h);
 }
 
 
@@ -1303,8 +1307,9 @@ __global__ void k_clear_u64_lists3(const int32_t* __restrict__ l0, const int* c0
 }
 void launch_clear_u64_lists3(const int32_t* l0, const int* c0, uint64_t* a0, const int32_t* l1, const int* c1,
                              uint64_t* a1, const int32_t* l2, const int* c2, uint64_t* a2, hipStream_t s,
-                             RoundState* st) {
-    hipLaunchKernelGGL(k_clear_u64_lists3, dim3(512), dim3(256), 0, s, l0, c0, a0, l1, c1, a1, l2, c2, a2, st);
+                             RoundState* st, int grid) {
+    hipLaunchKernelGGL(k_clear_u64_lists3, dim3(grid > 0 ? grid : 128), dim3(256), 0, s, l0, c0, a0, l1, c1, a1, l2,
+                       c2, a2, st);
 }
 
 

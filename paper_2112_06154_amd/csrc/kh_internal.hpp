@@ -18,8 +18,12 @@ constexpr int kPullChunk = 128;
 // Arcs per chunk of the frontier-expansion kernels.
 constexpr int kExpandChunk = 256;
 // A hop of the R-mask BFS pulls (every alive vertex scans its neighbours) once
-// its frontier's arcs exceed 1 / kRbfsPullRatio of all arcs; below that it pushes.
+// its frontier's arcs exceed 1 / kRbfsPullRatio of all arcs; below that it
+// pushes.  A packed union of many graphs uses kRbfsPullRatioUnion: its
+// frontiers are spread over many components, and a pull scans every vertex
+// of the union.
 constexpr int kRbfsPullRatio = 32;
+constexpr int kRbfsPullRatioUnion = 4;
 // In a pulled hop a thread scans a vertex of at most kRbfsLight arcs; the arcs
 // of a larger one are scanned by its whole wave.
 constexpr int kRbfsLight = 32;
@@ -34,6 +38,10 @@ constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 // Threads of a union work-group and the largest hash table (entries) that fits
 // the LDS budget of one work-group.
 constexpr int kUnionThreads = 256;
+// one-wave blocks of the union kernel for vertices of at most kUnionSmall
+// neighbours (most vertices of a power-law graph): a smaller hash table, so more
+// of them are in flight per CU, and no block-wide barriers across waves
+constexpr int kUnionSmall = 64;
 // block size of the union kernel for hubs (more than kHubDegree neighbours)
 constexpr int kUnionHubThreads = 1024;
 // Vertices with more neighbours than this order their arcs by list head rank in the union.
@@ -70,7 +78,7 @@ struct RoundState {
     int overflow;            // an estimate exceeded the representable range
     long long min_inexact;   // lazy exact peel: smallest bound of an inexact alive vertex
     int stall;               // lazy exact peel: a commit sequence waits for exact recomputations
-    int pad_stall;
+    int pull_ratio;          // lazy exact peel: a mask-BFS hop pulls once its frontier holds > 1/pull_ratio of the arcs (0: never)
     unsigned long long te;     // edges traversed (exact h-degree work)
     unsigned long long arcs;   // adjacency entries read by the h-degree kernels
     unsigned long long elems;  // sample-list entries read by the union kernels
@@ -84,7 +92,7 @@ struct RoundState {
     int unit_count;                  // sampled peel: work items of the hub launch (whole hubs and slices)
     int slot_count;                  // sampled peel: partial-list slots taken by hub slices
     int giant_count;                 // sampled peel: hubs split into slices
-    int pad_units;
+    int small_count;                 // sampled peel: worklist vertices merged by one-wave blocks
 };
 
 // Optional HIP-event timing of every launch of a kernel, on the stream it is
@@ -128,9 +136,10 @@ void launch_kill_list(const int32_t* list, const int* count, uint8_t* alive, hip
 // Chunk queue over the adjacency of list[*lo .. *hi) (lo/hi may be NULL: 0 and count).
 // arcs (nullable): adds the listed vertices' degrees.  pull_st (nullable): does
 // nothing when that round state's mask-BFS hop pulls (see launch_rbfs_hop).
+// grid (0: 128 blocks): blocks of the launch.
 void launch_enqueue(const int32_t* list, const int* lo, const int* hi, const int32_t* rp, int32_t* qv, int32_t* qb,
                     int* qcount, hipStream_t s, long long* arcs = nullptr, const RoundState* pull_st = nullptr,
-                    int64_t nnz = -1);
+                    int64_t nnz = -1, int grid = 0);
 // mode 0: mark alive unmarked neighbours with `epoch` and append them to out[*out_count++]
 // mode 1: decrement adeg of alive neighbours
 void launch_expand(const int32_t* qv, const int32_t* qb, const int* qcount, const int32_t* rp, const int32_t* col,
@@ -177,13 +186,13 @@ void launch_enqueue_r(const int32_t* rlist, const int* rcount, const int32_t* rp
 // hop t: hopfill[t] = aff_fill, qcount = 0, hop_arcs = next_arcs (next_arcs =
 // 0), and for t < h a new frontier epoch and fcount[(t+1)&1] = 0.
 void launch_clear_hop_end(const int32_t* list, const int* count, uint64_t* arr, uint32_t* fbits, RoundState* st,
-                          int* hopfill, int t, int h, hipStream_t s);
+                          int* hopfill, int t, int h, hipStream_t s, int grid = 0);
 // arr_k[list_k[i]] = 0 for three (list, count, array) triples at once; with
 // st != NULL the last block then resets the round state for the next round
 // (unless the sequence is stalled).
 void launch_clear_u64_lists3(const int32_t* l0, const int* c0, uint64_t* a0, const int32_t* l1, const int* c1,
                              uint64_t* a1, const int32_t* l2, const int* c2, uint64_t* a2, hipStream_t s,
-                             RoundState* st = nullptr);
+                             RoundState* st = nullptr, int grid = 0);
 // Picks the inexact alive vertices with deg <= st->hi as the next sources (at
 // most cap).  seg (nullable): segment (graph) of every vertex of a packed union;
 // then each source also gets a bit position sbit[slot] that is unique within its
@@ -207,7 +216,7 @@ void launch_rbfs_hop(const int32_t* qv, const int32_t* qb, const int* qcount, in
                      const int32_t* col, const uint8_t* alive, const uint64_t* gain_cur, const uint32_t* fbits_cur,
                      uint64_t* rmask, uint64_t* gain_next, uint32_t* fbits_next, int32_t* mark, int32_t* fmark,
                      int32_t* fnext, int* fnext_count, int32_t* alist, int* aff_fill, RoundState* st, int64_t nnz,
-                     hipStream_t s, PullTimer* timer = nullptr);
+                     hipStream_t s, PullTimer* timer = nullptr, int grid = 0);
 // exact decrement for vertices at distance exactly h (deg -= |R within h|), bound otherwise
 void launch_decay_masked(const int32_t* alist, RoundState* st, const int* hopfill, int h, const uint8_t* alive,
                          const int32_t* adeg, const int32_t* anchor, const uint64_t* rmask, int64_t* deg,
@@ -329,7 +338,8 @@ void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const
                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, int hash_log2,
                   LevelView prev, LevelView cur, int32_t* cursor, int32_t* order, int32_t* changed,
                   int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer = nullptr,
-                  const int32_t* hubs = nullptr, const int* hub_count = nullptr, const HubSplit* split = nullptr);
+                  const int32_t* hubs = nullptr, const int* hub_count = nullptr, const HubSplit* split = nullptr,
+                  const int32_t* smalls = nullptr, const int* small_count = nullptr, int hash_log2_small = 0);
 // Propagate the deletions and changes of level i-1 over the arcs of the queued
 // vertices: mark + append alive neighbours, fold the highest lost rank into
 // lostmax[], and keep m[.,i] current.
@@ -339,12 +349,14 @@ void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount
                          RoundState* st, hipStream_t s);
 // Keep only the worklist vertices whose list can change.
 // hubs (nullable): vertices with more than kHubDegree neighbours that need a
-// re-merge go to this list instead of rc.
+// re-merge go to this list instead of rc; smalls (nullable): those with at most
+// kUnionSmall neighbours go to smalls.
 // active (nullable): vertices with active[v] == 0 (not yet initialised at this
 // level) are never re-merged.
 void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int32_t* lostmax, int32_t* rc,
                      int* rc_count, hipStream_t s, const int32_t* rp = nullptr, int32_t* hubs = nullptr,
-                     int* hub_count = nullptr, const uint8_t* active = nullptr);
+                     int* hub_count = nullptr, const uint8_t* active = nullptr, int32_t* smalls = nullptr,
+                     int* small_count = nullptr);
 // Lazy initialisation of level h (Sec. 5): d[v] = a lower bound on the estimate
 // from the level h-1 lists of v's alive neighbours (prev), for the inactive
 // vertices of the list (NULL: all); resets their lostmax.

@@ -562,8 +562,9 @@ __global__ __launch_bounds__(BS) void k_union(const int32_t* __restrict__ workli
             }
         }
         if (tid == 0) {
+            // no key ranks above htop (it bounds r[v] and every list head)
             int run = 0, hr = 0;
-            for (int L = 255; L >= k; --L) {
+            for (int L = htop; L >= k; --L) {
                 const int c = hist[L];
                 if (c > 0 && run == 0) hr = L;
                 hist[L] = run;
@@ -782,8 +783,9 @@ __global__ __launch_bounds__(BS) void k_union_merge(const int* giant_count, cons
             }
         }
         if (tid == 0) {
+            // no key ranks above htop (it bounds r[v] and every list head)
             int run = 0, hr = 0;
-            for (int L = 255; L >= k; --L) {
+            for (int L = htop; L >= k; --L) {
                 const int c = hist[L];
                 if (c > 0 && run == 0) hr = L;
                 hist[L] = run;
@@ -845,7 +847,8 @@ void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const
                   const uint8_t* alive, const uint8_t* rank, int32_t M, const int32_t* Mv, int hash_log2,
                   LevelView prev, LevelView cur, int32_t* cursor, int32_t* order, int32_t* changed,
                   int* changed_count, RoundState* st, hipStream_t s, PullTimer* timer, const int32_t* hubs,
-                  const int* hub_count, const HubSplit* split) {
+                  const int* hub_count, const HubSplit* split, const int32_t* smalls, const int* small_count,
+                  int hash_log2_small) {
     if (n <= 0) return;
     const int grid = worklist ? 4096 : grid_for(n, 1, 16384);
     const size_t lds = sizeof(uint32_t) << hash_log2;
@@ -865,12 +868,20 @@ void launch_union(const int32_t* worklist, const int* wl_count, int32_t n, const
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             (void)hipFuncSetAttribute((const void*)k_union_merge<kMergeThreads>,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipFuncSetAttribute((const void*)k_union<kUnionSmall>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             lds_set[dev] = lds;
         }
     }
     const bool timed = timer && timer->used < timer->cap;
     if (timed) (void)hipEventRecord(timer->ev[2 * timer->used], s);
     const HubSplit none{};
+    // vertices of at most kUnionSmall neighbours: one wave each, a hash table
+    // sized for that block width
+    if (smalls)
+        hipLaunchKernelGGL(k_union<kUnionSmall>, dim3(8192), dim3(kUnionSmall), sizeof(uint32_t) << hash_log2_small, s,
+                           smalls, small_count, n, rp, col, alive, rank, M, Mv, hash_log2_small, prev, cur, cursor,
+                           order, changed, changed_count, st, none);
     hipLaunchKernelGGL(k_union<kUnionThreads>, dim3(grid), dim3(kUnionThreads), lds, s, worklist, wl_count, n, rp, col,
                        alive, rank, M, Mv, hash_log2, prev, cur, cursor, order, changed, changed_count, st, none);
     // hubs of the worklist: wider blocks for their neighbour walks; split into
@@ -961,7 +972,7 @@ void launch_expand_lists(const int32_t* qv, const int32_t* qb, const int* qcount
 __global__ void k_classify(const int32_t* __restrict__ wl, const int* wl_count, LevelView cur,
                            int32_t* __restrict__ lostmax, int32_t* __restrict__ rc, int* rc_count,
                            const int32_t* __restrict__ rp, int32_t* __restrict__ hubs, int* hub_count,
-                           const uint8_t* __restrict__ active) {
+                           const uint8_t* __restrict__ active, int32_t* __restrict__ smalls, int* small_count) {
     const int total = *wl_count;
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x; base < total; base += stride) {
@@ -980,18 +991,23 @@ __global__ void k_classify(const int32_t* __restrict__ wl, const int* wl_count, 
                 else need = true;
             }
         }
-        const bool hub = need && hubs && rp[v + 1] - rp[v] > kHubDegree;
-        const int slot = wave_append_slot(need && !hub, rc_count);
-        if (need && !hub) rc[slot] = v;
+        const int32_t deg = need && (hubs || smalls) ? rp[v + 1] - rp[v] : 0;
+        const bool hub = need && hubs && deg > kHubDegree;
+        const bool sm = need && smalls && deg <= kUnionSmall;
+        const bool mid = need && !hub && !sm;
+        const int slot = wave_append_slot(mid, rc_count);
+        if (mid) rc[slot] = v;
         const int hs = wave_append_slot(hub, hub_count);
         if (hub) hubs[hs] = v;
+        const int ss = wave_append_slot(sm, small_count);
+        if (sm) smalls[ss] = v;
     }
 }
 void launch_classify(const int32_t* wl, const int* wl_count, LevelView cur, int32_t* lostmax, int32_t* rc,
                      int* rc_count, hipStream_t s, const int32_t* rp, int32_t* hubs, int* hub_count,
-                     const uint8_t* active) {
+                     const uint8_t* active, int32_t* smalls, int* small_count) {
     hipLaunchKernelGGL(k_classify, dim3(1024), dim3(256), 0, s, wl, wl_count, cur, lostmax, rc, rc_count, rp, hubs,
-                       hub_count, active);
+                       hub_count, active, smalls, small_count);
 }
 
 // ---- lazy initialisation of the top level (Sec. 5, first heuristic) ---------------------

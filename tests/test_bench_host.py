@@ -70,3 +70,26 @@ def test_percentile_and_gpu_count_guard(capsys, monkeypatch):
         bench.main()
     assert e.value.code == 2
     assert "one GPU" in capsys.readouterr().out
+
+
+def test_trace_hops_numbers_hops_from_each_round(tmp_path, capsys):
+    # two rounds at h = 3: hop durations 7, 14, 21 us, then a round of one hop
+    p = tmp_path / "trace.csv"
+    with open(p, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        t = 0
+        for hops in (3, 3, 1):
+            w.writerow(["kh::k_select_commit(long const*)", t, t + 1000])
+            t += 2000
+            for hop in range(hops):
+                w.writerow(["kh::k_rbfs_hop(int const*)", t, t + (hop + 1) * 7000])
+                t += 50000
+            w.writerow(["kh::k_decay_masked(int const*)", t, t + 500])
+            t += 1000
+    bench.trace_hops(str(p))
+    out = json.loads(capsys.readouterr().out)
+    assert out["hops"]["1"]["dispatches"] == 3 and out["hops"]["1"]["avg_us"] == 7.0
+    assert out["hops"]["2"]["dispatches"] == 2 and out["hops"]["2"]["avg_us"] == 14.0
+    assert out["hops"]["3"]["dispatches"] == 2 and out["hops"]["3"]["avg_us"] == 21.0
+    assert sum(b["dispatches"] for b in out["buckets_us"].values()) == 7
