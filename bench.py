@@ -69,7 +69,7 @@ def measured_traffic(k, stages, hs):
 # the dispatches counted as one launch of a reported kernel (the union's hubs
 # are merged by a second, wider variant inside the same timed launch)
 KERNEL_NAMES = {0: ["k_ms_pull<16>", "k_ms_pull<8>", "k_ms_pull<4>", "k_ms_pull<2>", "k_ms_pull<1>"],
-                1: ["k_union<256>", "k_union<1024>", "k_hub_units", "k_union_merge<256>"],
+                1: ["k_union<256>", "k_union<64>", "k_union<1024>", "k_hub_units", "k_union_merge<256>"],
                 2: ["k_rbfs_hop"]}
 # FETCH_SIZE reads 524,317 KiB for the 1 GiB read by the add kernel of
 # --copy-calib, WRITE_SIZE 1,048,576 KiB for its 1 GiB write
@@ -651,7 +651,10 @@ def main():
     warm_done = 0
     for i in range(args.warmup):
         left = args.budget_s - elapsed_total() - reserve
-        if left < 2.0 * est:
+        # timed steps come first: a warmup step beyond the first runs only if
+        # every requested timed step still fits after it
+        need = 2.0 * est if warm_done == 0 else est * 1.05 * (args.steps + 1)
+        if left < need:
             log(f"[{elapsed_total():.0f}s] warmup cut at {warm_done} step(s): {left:.0f}s left, step ~{est:.0f}s")
             break
         t = time.perf_counter()
