@@ -11,7 +11,9 @@
  *   - Graphs are simple and undirected, given as int32 CSR: row_ptr[n+1] with
  *     row_ptr[0] = 0 and row_ptr[n] = nnz = 2m, col[nnz] holding both arc
  *     directions, each adjacency sorted ascending, no self-loops, no
- *     duplicates.  Vertex ids are 0..n-1.
+ *     duplicates.  Vertex ids are 0..n-1.  nnz <= 2^31 - 2^24 - 1 (arc indices
+ *     are int32 on the device, with headroom for chunked arc ranges); a larger
+ *     nnz is KH_EINVAL.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls that take
  *     one enqueue their GPU work on it; calls that return results in host
  *     memory synchronise that stream before returning.
@@ -176,7 +178,7 @@ kh_status kh_core(kh_graph *g, const kh_params *params, int32_t *core_out, kh_re
  *     arcs_scanned, list_elements and seconds describe the packed union the
  *     graph was part of (equal across its graphs).
  * Graphs are packed in order of size into unions of at most 2^24 - 1 vertices
- * (sampled) or 2^31 - 2 vertices and 2^31 - 1 arcs (exact); a batch runs as
+ * (sampled) or 2^31 - 2 vertices and 2^31 - 2^24 - 1 arcs (exact); a batch runs as
  * consecutive unions.
  * Errors: as kh_core; KH_ENOTIMPL with KH_EARLY_STOP (its stopping test is per
  * graph).  On error no result of the batch is valid. */

@@ -305,7 +305,7 @@ extern "C" int64_t kh_buffer_size(int64_t n, double epsilon, double delta, int32
 }
 
 extern "C" kh_status kh_validate_csr(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t* col) {
-    if (n < 0 || nnz < 0 || nnz > INT32_MAX) return KH_EINVAL;
+    if (n < 0 || nnz < 0 || nnz > kMaxArcs) return KH_EINVAL;
     if (!row_ptr || (nnz > 0 && !col)) return KH_EINVAL;
     if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz) return KH_EGRAPH;
     for (int32_t v = 0; v < n; ++v) {
@@ -500,7 +500,7 @@ void canonicalize(int32_t n, int64_t nnz, const int32_t* row_ptr, const int32_t*
 
 extern "C" kh_status kh_graph_load_csr(kh_context* ctx, int32_t n, int64_t nnz, const int32_t* row_ptr,
                                        const int32_t* col, uint32_t flags, void* stream, kh_graph** out) {
-    if (!ctx || !out || n < 0 || nnz < 0 || nnz > INT32_MAX) return KH_EINVAL;
+    if (!ctx || !out || n < 0 || nnz < 0 || nnz > kMaxArcs) return KH_EINVAL;
     *out = nullptr;
     if (!row_ptr || (nnz > 0 && !col)) return KH_EINVAL;
     const bool borrow = (flags & KH_PTRS_DEVICE_BORROW) != 0;
@@ -1352,7 +1352,8 @@ struct SampledRun {
         int64_t sl = kHubSlice;
         if (const char* e = std::getenv("KH_HUB_SLICE")) sl = std::atoll(e);
         if (sl <= 0 || h < 2 || g->nnz <= 2 * (int64_t)sl) return;
-        sl = std::min<int64_t>(sl, INT32_MAX);
+        // (one slice's arc range must not overflow int32 past the last arc)
+        sl = std::min<int64_t>(sl, kMaxHubSlice);
         // a split hub has more than sl arcs and at most deg / sl + 1 slices
         const int64_t slots = 2 * (g->nnz / sl) + 1;
         const int64_t ucap = g->nnz / (kHubDegree + 1) + 1 + slots;
@@ -2081,7 +2082,7 @@ extern "C" kh_status kh_core_batch(kh_context* ctx, int32_t count, kh_graph* con
         std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return graphs[a]->n < graphs[b]->n; });
         for (int32_t i : idx) {
             kh_graph* g = graphs[i];
-            if (vn + g->n > vmax || an + g->nnz > (int64_t)INT32_MAX) flush();
+            if (vn + g->n > vmax || an + g->nnz > kMaxArcs) flush();
             cg.push_back(g);
             co.push_back(core_outs[i]);
             ci.push_back(i);

@@ -101,3 +101,13 @@ def test_batch_and_serve_reject_missing_arguments():
     assert L.kh_serve_wait(None, 1, ctypes.byref(res)) == -1
     assert L.kh_serve_cancel(None, 1) == -1
     assert L.kh_serve_stop(None) == -1
+
+
+def test_validate_csr_rejects_arc_counts_beyond_the_int32_headroom():
+    # arc indices are int32 on the device with 2^24 of headroom for chunked ranges
+    limit = 2**31 - 1 - 2**24
+    L = kh.lib()
+    rp = np.zeros(2, np.int32)
+    col = np.zeros(1, np.int32)
+    assert L.kh_validate_csr(1, limit + 1, rp.ctypes.data, col.ctypes.data) == kh.KH_EINVAL
+    assert L.kh_validate_csr(1, 2**31 - 1, rp.ctypes.data, col.ctypes.data) == kh.KH_EINVAL
