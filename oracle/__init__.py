@@ -22,6 +22,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "khoracle.c")
 _LIB = os.path.join(_HERE, "libkhoracle.so")
+# KH_ORACLE_LIB: an oracle library built elsewhere from the same source (the
+# sanitizer test loads an ASan/UBSan build this way); used as given, not rebuilt
+_LIB_OVERRIDE = os.environ.get("KH_ORACLE_LIB")
 _lib = None
 
 
@@ -38,9 +41,12 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i64, u64, u32, dbl, ci = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, ctypes.c_int
         L.orc_splitmix64.argtypes = [u64]

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libkhcore.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["kh_graph.hip", "kh_msbfs.hip", "kh_union.hip", "kh_noalloc.hip", "kh_order.hip", "kh_host.cpp",
+SOURCES = ["kh_graph.hip", "kh_msbfs.hip", "kh_union.hip", "kh_noalloc.hip", "kh_order.hip", "kh_csr.cpp", "kh_host.cpp",
            "kh_serve.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

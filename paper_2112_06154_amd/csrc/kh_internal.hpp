@@ -7,6 +7,7 @@
 #include <cstdint>
 
 #include "../../include/khcore.h"
+#include "kh_csr.hpp"
 
 namespace kh {
 
@@ -46,10 +47,7 @@ constexpr int kUnionSmall = 64;
 constexpr int kUnionHubThreads = 1024;
 // Vertices with more neighbours than this order their arcs by list head rank in the union.
 constexpr int kHubDegree = 1024;
-// Arc indices are int32 in the kernels, which step through arc ranges in
-// chunks (at most a hub slice, 2^23 arcs) that may end past the last arc:
-// graphs and packed unions hold at most this many arcs so none overflows.
-constexpr int64_t kMaxArcs = (int64_t)INT32_MAX - ((int64_t)1 << 24);
+// Largest hub slice (kMaxArcs, in kh_csr.hpp, leaves room for it).
 constexpr int64_t kMaxHubSlice = (int64_t)1 << 23;
 // Arcs per slice of a hub merged in parallel (more arcs: split; see HubSplit).
 constexpr int kHubSlice = 8192;
