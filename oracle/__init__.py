@@ -9,7 +9,8 @@ The arithmetic lives in ``khoracle.c`` (plain C, compiled with gcc into
 Definitions follow Tatti, arXiv 2112.06154: Sec. 2 (h-neighbourhoods,
 (k,h)-cores, ExactCore), Sec. 3 (Eq. buffer, ranks, B[v,i]/k[v,i]),
 Def. est in Sec. 4 (the estimator), Alg. 4 (Core) and Sec. 6 (h-density,
-densest core level).
+densest core level).  ``oracle.refined`` runs Alg. 4 on the refined
+bookkeeping of Sec. 5 (Alg. 5 and 6) in plain Python, for small graphs.
 """
 from __future__ import annotations
 
