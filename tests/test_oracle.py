@@ -311,6 +311,25 @@ def test_sampled_estimate_is_approx():
     assert np.all(np.abs(est - d) <= eps * d + 1e-9)
 
 
+def test_estimate_guarantee_over_200_seeds():
+    # Prop. approx with the union bound behind C = log(2n/delta) (Eq. buffer):
+    # with the paper's M, the probability over the ranks that any vertex's
+    # estimate misses deg_h by more than eps is at most delta.
+    g = gg.barabasi_albert(3000, 3, seed=8)
+    eps, delta = 0.5, 0.05
+    M = oracle.M_int(g.n, eps, delta)
+    d = oracle.hdeg(g, 3).astype(np.float64)
+    assert (d > M).sum() > 1000  # most estimates are sampled
+    bad = 0
+    worst = 0.0
+    for seed in range(200):
+        est = oracle.estimate_all(g, 3, oracle.ranks(g.n, seed), M).astype(np.float64)
+        rel = np.max(np.abs(est - d) / np.maximum(d, 1.0))
+        worst = max(worst, rel)
+        bad += rel > eps
+    assert bad <= delta * 200, (bad, worst)
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_sampled_lists_match_compute_recursion(seed):
     # Closed form of B[v,i], k[v,i] (Sec. 3) equals the Compute recursion of
