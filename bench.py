@@ -10,7 +10,8 @@ timed region.  One step runs the whole hot path at h = 2 and h = 3 (--hs):
            bulk peel, densest core level (pruning variant)
   sampled  Core (Alg. 4, eps = 0.5, delta = 0.05): ranks, sample-list union
            over h hops, estimate, bulk peel with lazy update, densest-core
-           estimate (Alg. 7, core levels, pruning variant)
+           estimate (Alg. 7, core levels, pruning variant); the top level is
+           initialised lazily at the h listed in --lazy-hs (3 by default)
 
 Metric: edges traversed per second of ExactCore, from the library's own count
 (kh_result.edges_traversed: for every h-degree the peel evaluates, the arcs a
@@ -21,7 +22,9 @@ second.  ms_per_step is the wall time of the whole step.
 
 The run keeps to a wall-clock budget (--budget-s, counted from the start of
 the process): warmup and timed steps are cut to what fits, at least one timed
-step, and the JSON line reports the counts actually run.  The JSON line also
+step, and the JSON line reports the counts actually run.  Timed steps come
+first: a warmup step beyond the first runs only if every requested timed step
+still fits after it.  The JSON line also
 carries the roofline of the dominant instrumented kernel (HIP events on its
 launch stream inside the library, algorithmic bytes counted by the kernel) and
 the CPU oracle's rate on a bounded sample of sources, over all host cores.
